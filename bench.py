@@ -1,0 +1,225 @@
+"""Benchmark: splatted points per second for forward+backward trilinear point splatting.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
+
+Workload (one step = the whole hot path once): 2M points drawn from 64 anisotropic Gaussian
+clusters plus 30% on planar patches, one 1920x1080 pinhole view, 8 pyramid layers,
+4-channel float32 descriptors, upstream pyramid gradient N(0, 1); forward (projection,
+layer pair, trilinear write, per-texel depth sort, top-16, blend) then backward (gradients
+for positions, world sizes, opacities and descriptors).  Synthetic, seeded inputs resident
+in HBM before the timed region.
+
+Also reported: per-kernel durations (HIP events around every launch, on its stream), the
+roofline of the dominant kernel, the CPU oracle on the same workload, and the batched
+multi-view form (16 views of mixed resolution over 4M points, one graph launch per step)
+against 16 single-view launch sequences.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "splatted points/sec fwd+bwd at 1080p (+ % HBM roofline), batched vs per-view"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PARAMS = ("x", "y", "z", "sw", "alpha", "desc")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(stage, N, V, D, E, K, P, Ppad, nblk, NB):
+    """Algorithmic bytes one launch of `stage` must move (reads + writes), for the report.
+
+    N points, V views, D channels, E tile entries, K kept fragments (sum of min(n, 16)),
+    P texels, Ppad texels incl. tile padding, nblk point blocks, NB tiles."""
+    ent, row = 24 * E, 4 * (4 + D) * E
+    table = {
+        "count": 16 * N + 4 * nblk * NB,
+        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + ent,
+        "fwd_items": ent + 4 * D * K + 4 * D * P + 4 * Ppad + 12 * K,
+        "bwd_pixels": 4 * Ppad + 12 * K + 4 * D * P + 4 * D * K + 8 * K,
+        "bwd_items": ent + 4 * Ppad + 16 * K + 4 * D * P + row,
+        "bwd_points": 20 * N + row + 4 * (5 + D) * N,
+        "colscan": 8 * nblk * NB + 4 * NB,
+    }
+    return table.get(stage)
+
+
+def step_bytes(N, Nv, D, F, K, P):
+    """Whole-step algorithmic bytes of the method (one view, fwd+bwd, fragment lists
+    materialised once): point reads, descriptor reads of visible points, fragment write and
+    read, kept ids saved and reloaded, pyramid write and upstream-gradient read, point
+    re-read in backward, gradient write."""
+    return N * 20 + Nv * 4 * D + 16 * F + 8 * K + 8 * D * P + Nv * (20 + 4 * D) + N * (20 + 4 * D)
+
+
+def cpu_baseline(sc, G):
+    """The CPU oracle (single-threaded C) on the full workload: one forward + backward."""
+    import numpy as np
+    from oracle import oracle
+    cam, nl = sc["cams"][0], sc["nlayers"]
+    n = len(sc["points"]["x"])
+    Gd = G.astype(np.float64).reshape(-1, sc["D"])
+    t0 = time.perf_counter()
+    oracle.forward(sc["points"], cam, nl)
+    oracle.backward(sc["points"], cam, nl, Gd)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": "one forward+backward of the full workload (%d points, %dx%d, %d layers), "
+                      "single thread, %.1f s" % (n, cam["W"], cam["H"], nl, dt)}
+
+
+def run_batched(torch, tp, scenes, steps, warmup, dev):
+    """16 views of mixed resolution over 4M points: one graph launch per step vs 16
+    single-view forward+backward sequences on the same stream."""
+    sc = scenes.multiview_scene(4, n=4_000_000, views=16, nlayers=8)
+    n = len(sc["points"]["x"])
+    t = {k: torch.from_numpy(sc["points"][k]).to(dev) for k in PARAMS}
+    args = [t[k] for k in PARAMS]
+    rb = tp.Renderer(sc["cams"], sc["nlayers"], sc["D"], n, device=dev)
+    G = torch.from_numpy(scenes.upstream_gradient(4, rb.pyramid_numel())).to(dev)
+    pyr = torch.empty(rb.pyramid_numel(), device=dev)
+    grads = [torch.empty(n, device=dev) for _ in range(5)] + [torch.empty((n, sc["D"]), device=dev)]
+    plan = tp.Plan(rb, *args, pyr, G, grads)
+    singles, offs, o = [], [], 0
+    big = max(range(16), key=lambda v: sc["cams"][v]["W"] * sc["cams"][v]["H"])
+    first = tp.Renderer([sc["cams"][big]], sc["nlayers"], sc["D"], n, device=dev)
+    for cam in sc["cams"]:
+        # the single-view calls run one after another: they share the largest buffers
+        r = tp.Renderer([cam], sc["nlayers"], sc["D"], n, device=dev, share_buffers_with=first)
+        singles.append(r)
+        offs.append((o, o + r.pyramid_numel()))
+        o += r.pyramid_numel()
+    Gs = [G[a:b].contiguous() for (a, b) in offs]
+
+    def per_view():
+        for r, g in zip(singles, Gs):
+            r.forward(*args)
+            r.backward(*args, g)
+
+    def batched():
+        plan.launch(forward=True, backward=True)
+
+    res = {}
+    for name, fn in (("per_view", per_view), ("batched", batched)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / steps
+    return {"workload": "clusters4m_16views_mixed_640x480_to_1920x1080_fwd_bwd", "points": n,
+            "views": 16, "steps": steps, "per_view_ms": res["per_view"],
+            "batched_graph_ms": res["batched"], "speedup": res["per_view"] / res["batched"],
+            "batched_points_per_s": n * 16 / (res["batched"] / 1e3),
+            "per_view_points_per_s": n * 16 / (res["per_view"] / 1e3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this renderer runs on one GPU; multi-GPU runs are not part of this "
+              "build (views would shard across GPUs with one gradient all-reduce).", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2401_06003_amd as tp
+    import scenes
+
+    dev = torch.device("cuda:0")
+    log("generating the 2M-point scene")
+    sc = scenes.cluster_scene(2)
+    cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
+    N = len(sc["points"]["x"])
+    t = {k: torch.from_numpy(sc["points"][k]).to(dev) for k in PARAMS}
+    pargs = [t[k] for k in PARAMS]
+    r = tp.Renderer([cam], nl, D, N, device=dev)
+    Gnp = scenes.upstream_gradient(3, r.pyramid_numel())
+    G = torch.from_numpy(Gnp).to(dev)
+    pyr = torch.empty(r.pyramid_numel(), device=dev)
+    grads = [torch.empty(N, device=dev) for _ in range(5)] + [torch.empty((N, D), device=dev)]
+
+    def step():
+        r.forward(*pargs, out=pyr)
+        r.backward(*pargs, G, outs=grads)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = r.stats()
+    counts, _ids = r.export_fragments()
+    c64 = counts.to(torch.int64)
+    F = int(c64.sum().item())
+    K = int(torch.clamp(c64, max=tp.KEEP).sum().item())
+    E, NB = st["entries"], st["bins"]
+    P = r.texels
+    Ppad = NB * 256
+    nblk = (N + 4095) // 4096
+    Nv = st["visible"]  # points that wrote at least one fragment
+
+    log("timed %d steps" % args.steps)
+    tp.timing_enable(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stages = tp.timing_read()
+    tp.timing_enable(False)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0}
+    dom = max((k for k in stage_ms if kernel_bytes(k, N, 1, D, E, K, P, Ppad, nblk, NB)),
+              key=lambda k: stage_ms[k])
+    dom_bytes = kernel_bytes(dom, N, 1, D, E, K, P, Ppad, nblk, NB)
+    achieved = dom_bytes / (stage_ms[dom] / 1e3) / 1e9
+    sbytes = step_bytes(N, Nv, D, F, K, P)
+
+    out = {
+        "metric": METRIC, "value": N / (ms / 1e3), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "clusters2m_1920x1080_8layers_d4_fwd_bwd", "points": N, "views": 1,
+                   "width": cam["W"], "height": cam["H"], "layers": nl, "desc_dim": D},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dom_bytes, "ms_per_launch": stage_ms[dom]},
+        "step_effective_hbm_frac": sbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "step_algorithmic_bytes": sbytes,
+        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "fragments": F, "kept_fragments": K, "tile_entries": E, "tiles": NB, "texels": P,
+        "visible_points": Nv,
+    }
+    if not args.no_batched:
+        log("batched vs per-view (16 views, 4M points)")
+        out["batched"] = run_batched(torch, tp, scenes, max(3, args.steps // 4),
+                                     max(1, args.warmup // 2), dev)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one step)")
+        out["cpu_baseline"] = cpu_baseline(sc, Gnp)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * trips.h -- C ABI of the MI355X trilinear point-splatting library (libtrips.so).
+ *
+ * The library renders the differentiable trilinear point splatting of TRIPS
+ * (Franke, Rueckert, Fink, Stamminger, "TRIPS: Trilinear Point Splatting for
+ * Real-Time Radiance Field Rendering", 2024): the render function of Eq. 1 without
+ * the environment map, I = Phi(C, R, t, x, s_w, tau, alpha), whose output is a
+ * feature image pyramid, and its backward pass.
+ *
+ * Conventions for every entry point:
+ *  - Pointers to point data, outputs, `saved` and `workspace` are DEVICE pointers;
+ *    `*_host` arguments and the config / camera / tuning structs are HOST memory.
+ *  - The caller owns and allocates all memory.  The library never allocates device
+ *    memory, never synchronises the stream, and never throws across the ABI.
+ *  - Every argument is validated on the host before anything is launched; a call
+ *    that returns an error launched nothing.  HIP launch failures return
+ *    TRIPS_ERR_HIP and the HIP error code is kept for trips_last_hip_error().
+ *  - All work is enqueued on `stream` in order; results are ready when the stream is.
+ *  - Up to TRIPS_MAX_VIEWS views of arbitrary, different resolutions are rendered by
+ *    one call ("batched views"); every point is read once per call and projected
+ *    into every view.  Gradients are summed over the views of a call.
+ */
+#ifndef TRIPS_H
+#define TRIPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRIPS_MAX_VIEWS 16
+#define TRIPS_MAX_LAYERS 12
+#define TRIPS_KEEP 16 /* list clamp of Sec. 3.2: the 16 front-most fragments are blended */
+
+typedef enum {
+  TRIPS_OK = 0,
+  TRIPS_ERR_INVALID_ARG = -1, /* null pointer, bad size, bad camera or config */
+  TRIPS_ERR_WORKSPACE = -2,   /* workspace or saved buffer smaller than required */
+  TRIPS_ERR_CAPACITY = -3,    /* problem exceeds 32-bit fragment indexing */
+  TRIPS_ERR_HIP = -4,         /* a HIP call failed; see trips_last_hip_error() */
+  TRIPS_ERR_UNSUPPORTED = -5  /* valid but not built: max_list != 16, desc_dim not 4 or 8,
+                                 or too many tiles in one view */
+} trips_status;
+
+/* Pinhole camera (Sec. 3.1, Eq. 2), OpenCV axes (x right, y down, z forward).
+   World to camera: X_c = R * X_w + t, R row-major.  Screen: x = fx * X_c / Z_c + cx,
+   y = fy * Y_c / Z_c + cy, depth Z_c, screen size s = fx * s_w / Z_c.
+   Points with Z_c <= znear (znear > 0) or non-finite x, y, s are culled. */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height; /* layer 0 resolution; layer L is ceil(width/2^L) x ceil(height/2^L) */
+  float znear;
+} trips_camera;
+
+/* Renderer hyper-parameters (Sec. 3.1-3.2). */
+typedef struct {
+  int32_t num_layers; /* pyramid layers n, 1..TRIPS_MAX_LAYERS; texel size of layer L is 2^L */
+  int32_t max_list;   /* must be TRIPS_KEEP (16) */
+  float eps;          /* minimum layer weight for points smaller than a pixel (0.25) */
+  int32_t desc_dim;   /* descriptor channels D: 4 or 8 */
+} trips_config;
+
+/* Point cloud, structure of arrays, all float32 device arrays of length n; desc is
+   row-major [n][desc_dim].  size_w is the world-space size s_w; opacity is alpha. */
+typedef struct {
+  const float *x, *y, *z;
+  const float *size_w;
+  const float *opacity;
+  const float *desc;
+  int64_t n;
+} trips_points;
+
+/* Launch-shape choices (all optional: pass NULL for the defaults).  tile_w is the
+   width in texels of a screen tile (16x16 by default; tiles always hold 256 texels:
+   8x32, 16x16, 32x8, 64x4).  points_per_block is the number of points one binning
+   workgroup histograms (256..65535).  item_entries is the number of tile entries one
+   sort/blend workgroup consumes before handing over to a merge (256..65536). */
+typedef struct {
+  int32_t tile_w;
+  int32_t points_per_block;
+  int32_t item_entries;
+} trips_tuning;
+
+/* Host only.  Layer sizes of one view: dims_host[2L] = W_L, dims_host[2L+1] = H_L, and
+   offsets_host[L] = first texel of layer L in the concatenated pyramid of that view,
+   offsets_host[num_layers] = total texels.  Either output may be NULL. */
+trips_status trips_layer_layout(const trips_camera* cam_host, const trips_config* cfg_host,
+                                int32_t* dims_host, int64_t* offsets_host);
+
+/* Host only.  Bytes of the `workspace` (scratch, any call) and `saved` (written by the
+   forward pass, read by backward and export) buffers for `views` cameras and n points.
+   Both buffers must be 256-byte aligned. */
+trips_status trips_buffer_sizes(const trips_config* cfg_host, const trips_camera* cams_host,
+                                int32_t views, int64_t n, const trips_tuning* tuning_host,
+                                size_t* workspace_bytes, size_t* saved_bytes);
+
+/* Forward render (Eq. 1-7).  pyramid_out: float32, for each view in order, each layer
+   in order, row-major [H_L][W_L][D]; overwritten.  `saved` receives the per-texel list
+   lengths, the kept fragments (<= 16 per texel, front to back) and the tile entries,
+   which trips_backward and trips_export_fragments read. */
+trips_status trips_forward(const trips_config* cfg_host, const trips_points* pts_host,
+                           const trips_camera* cams_host, int32_t views,
+                           const trips_tuning* tuning_host, float* pyramid_out, void* saved,
+                           size_t saved_bytes, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream);
+
+/* Backward of sum(grad_pyramid * pyramid) for the forward call that filled `saved`
+   (same points, cameras, config and tuning).  grad_pyramid has the pyramid layout.
+   All six gradient outputs are device float32 arrays ([n], desc [n][D]) and are
+   OVERWRITTEN (culled points get 0).  The per-texel blend state is recomputed from the
+   kept fragments, not stored.  Sort order, culling and the 16-element clamp are
+   piecewise constant and carry no gradient. */
+trips_status trips_backward(const trips_config* cfg_host, const trips_points* pts_host,
+                            const trips_camera* cams_host, int32_t views,
+                            const trips_tuning* tuning_host, const float* grad_pyramid,
+                            const void* saved, size_t saved_bytes, void* workspace,
+                            size_t workspace_bytes, float* grad_x, float* grad_y, float* grad_z,
+                            float* grad_size_w, float* grad_opacity, float* grad_desc,
+                            hipStream_t stream);
+
+/* Parity export of the fragment lists of the forward call that filled `saved`.
+   counts: int32 [P] untruncated list length per texel; ids: int32 [P][16] kept point
+   indices front to back (depth ascending, ties by index), -1 padded.  P = texels of all
+   views and layers in pyramid order. */
+trips_status trips_export_fragments(const trips_config* cfg_host, const trips_camera* cams_host,
+                                    int32_t views, const trips_tuning* tuning_host,
+                                    const void* saved, size_t saved_bytes, int32_t* counts,
+                                    int32_t* ids, hipStream_t stream);
+
+/* Statistics of the forward call that filled `saved`, copied to host memory after a
+   stream synchronisation: stats_host[0] = tile entries, [1] = work items,
+   [2] = tiles (bins), [3] = (point, view) pairs that wrote at least one fragment.
+   For tests and reports; not needed for rendering. */
+trips_status trips_forward_stats(const trips_config* cfg_host, const trips_camera* cams_host,
+                                 int32_t views, const trips_tuning* tuning_host, const void* saved,
+                                 size_t saved_bytes, int64_t* stats_host, hipStream_t stream);
+
+const char* trips_status_string(trips_status status);
+int32_t trips_last_hip_error(void);
+
+/* Kernel timing for reports (host side only, per calling thread).  While enabled, every
+   kernel that trips_forward, trips_backward and trips_export_fragments launch outside a
+   graph capture is bracketed by two HIP events recorded on its launch stream.
+   trips_timing_read waits for those events and returns, per stage, the summed
+   milliseconds and the number of launches since the last read (or enable), then resets.
+   Stage k is named by trips_stage_name(k), k < TRIPS_NUM_STAGES.  The events are host
+   objects owned by the library; no device memory is allocated. */
+#define TRIPS_NUM_STAGES 12
+trips_status trips_timing_enable(int32_t enable);
+trips_status trips_timing_read(float* ms_host /*[TRIPS_NUM_STAGES]*/,
+                               int32_t* launches_host /*[TRIPS_NUM_STAGES]*/);
+const char* trips_stage_name(int32_t stage);
+
+/* ---------------------------------------------------------------------------------
+   Plan: the batched multi-view form captured once in a HIP graph and replayed.
+   Buffers are bound at creation; every launch replays the forward and/or backward
+   kernels for all views.  The plan owns only host objects (the graphs); all device
+   memory still comes from the caller.  trips_plan_create captures on `stream`, which
+   must be a created stream (not the null stream) with no capture in progress;
+   grad_pyramid may be NULL for a forward-only plan.  Launches may use any stream. */
+typedef struct trips_plan trips_plan;
+
+trips_status trips_plan_create(const trips_config* cfg_host, const trips_points* pts_host,
+                               const trips_camera* cams_host, int32_t views,
+                               const trips_tuning* tuning_host, float* pyramid_out, void* saved,
+                               size_t saved_bytes, void* workspace, size_t workspace_bytes,
+                               const float* grad_pyramid, float* grad_x, float* grad_y,
+                               float* grad_z, float* grad_size_w, float* grad_opacity,
+                               float* grad_desc, hipStream_t stream, trips_plan** plan_out);
+/* which: 1 = forward, 2 = backward, 3 = both (in that order). */
+trips_status trips_plan_launch(trips_plan* plan, int32_t which, hipStream_t stream);
+void trips_plan_destroy(trips_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIPS_H */

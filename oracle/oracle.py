@@ -47,11 +47,12 @@ def lib():
         L.oracle_fragments.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, c_int, c_int, c_double,
                                        c_int, i64, i64p, dp]
         L.oracle_fragments.restype = i64
+        u8p = ctypes.c_void_p
         L.oracle_forward.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int, c_int,
-                                     c_int, c_double, c_int, dp, i32p, i64p]
+                                     c_int, c_double, c_int, u8p, dp, i32p, i64p]
         L.oracle_forward.restype = c_int
         L.oracle_backward.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int, c_int,
-                                      c_int, c_double, c_int, dp, dp, dp, dp, dp, dp, dp]
+                                      c_int, c_double, c_int, u8p, dp, dp, dp, dp, dp, dp, dp]
         L.oracle_backward.restype = c_int
         _lib = L
     return _lib
@@ -116,10 +117,19 @@ def fragments(pts, cam, nlayers, eps=0.25, fp32=True):
             "z": reals[:nf, 3]}
 
 
-def forward(pts, cam, nlayers, maxlist=16, eps=0.25, fp32=True):
+def _mask_ptr(mask, P):
+    if mask is None:
+        return None, ctypes.c_void_p(0)
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+    assert m.shape == (P,)
+    return m, ctypes.c_void_p(m.ctypes.data)
+
+
+def forward(pts, cam, nlayers, maxlist=16, eps=0.25, fp32=True, mask=None):
     """One view.  Returns (pyr [P, D] float64, counts [P] int32, ids [P, maxlist] int64).
 
-    Rows are the texels of all layers concatenated, each layer row-major."""
+    Rows are the texels of all layers concatenated, each layer row-major.  With a [P]
+    boolean mask only those texels are evaluated (others stay 0 / -1)."""
     n = len(pts["x"])
     X, Y, Z, S, A = (_d(pts[k]) for k in ("x", "y", "z", "sw", "alpha"))
     desc = _d(pts["desc"]).reshape(n, -1) if n else np.zeros((0, pts["desc"].shape[-1]))
@@ -129,16 +139,18 @@ def forward(pts, cam, nlayers, maxlist=16, eps=0.25, fp32=True):
     pyr = np.zeros((P, D), dtype=np.float64)
     counts = np.zeros(P, dtype=np.int32)
     ids = np.zeros((P, maxlist), dtype=np.int64)
+    keep, mp = _mask_ptr(mask, P)
     rc = lib().oracle_forward(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(S), _ptr(A), _ptr(desc), D,
                               _ptr(cv), int(cam["W"]), int(cam["H"]), int(nlayers), int(maxlist),
-                              float(eps), int(fp32), _ptr(pyr), _ptr(counts, ctypes.c_int32),
+                              float(eps), int(fp32), mp, _ptr(pyr), _ptr(counts, ctypes.c_int32),
                               _ptr(ids, ctypes.c_int64))
     assert rc == 0, rc
     return pyr, counts, ids
 
 
-def backward(pts, cam, nlayers, G, maxlist=16, eps=0.25, fp32=True):
-    """One view: gradients of sum(G * pyramid).  G is [P, D].
+def backward(pts, cam, nlayers, G, maxlist=16, eps=0.25, fp32=True, mask=None):
+    """One view: gradients of sum(G * pyramid).  G is [P, D].  With a texel mask only
+    those texels contribute (exact for points whose texels are all in the mask).
 
     Returns dict gx, gy, gz, gsw, galpha [N] and gdesc [N, D] (float64)."""
     n = len(pts["x"])
@@ -150,13 +162,23 @@ def backward(pts, cam, nlayers, G, maxlist=16, eps=0.25, fp32=True):
     assert Gd.shape[0] == num_pixels(cam["W"], cam["H"], nlayers)
     out = {k: np.zeros(n, dtype=np.float64) for k in ("gx", "gy", "gz", "gsw", "galpha")}
     out["gdesc"] = np.zeros((n, D), dtype=np.float64)
+    keep, mp = _mask_ptr(mask, Gd.shape[0])
     rc = lib().oracle_backward(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(S), _ptr(A), _ptr(desc), D,
                                _ptr(cv), int(cam["W"]), int(cam["H"]), int(nlayers), int(maxlist),
-                               float(eps), int(fp32), _ptr(Gd), _ptr(out["gx"]), _ptr(out["gy"]),
+                               float(eps), int(fp32), mp, _ptr(Gd), _ptr(out["gx"]), _ptr(out["gy"]),
                                _ptr(out["gz"]), _ptr(out["gsw"]), _ptr(out["galpha"]),
                                _ptr(out["gdesc"]))
     assert rc == 0, rc
     return out
+
+
+def texel_index(cam, nlayers, L, i, j):
+    """Row of texel (i, j) of layer L in the concatenated pyramid of one view."""
+    dims = layer_dims(cam["W"], cam["H"], nlayers)
+    base = np.cumsum([0] + [w * h for w, h in dims])
+    L = np.asarray(L)
+    W = np.array([w for w, _ in dims])[L]
+    return base[L] + np.asarray(j) * W + np.asarray(i)
 
 
 def split_layers(flat, cam, nlayers):

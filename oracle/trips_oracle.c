@@ -159,7 +159,8 @@ static void project(const cam_t* c, double X, double Y, double Z, double sw, int
 
 /* Step 3: the 2x2 footprint of one layer entry; appends fragments. */
 static int64_t emit_layer(const cam_t* c, const proj_t* p, int sel, int64_t idx, double alpha,
-                          int fp32, const int64_t* layer_base, frag_t* out, int64_t nout) {
+                          int fp32, const int64_t* layer_base, const uint8_t* mask, frag_t* out,
+                          int64_t nout) {
   int L = p->L[sel];
   int WL = layer_w(c->W, L), HL = layer_w(c->H, L);
   double u, v, fu, fv;
@@ -190,8 +191,10 @@ static int64_t emit_layer(const cam_t* c, const proj_t* p, int sel, int64_t idx,
       if (i < 0 || i >= WL || j < 0 || j >= HL) continue;
       double wx = wxs[di], wy = wys[dj];
       if (wx == 0.0 || wy == 0.0) continue;
+      int64_t pix = layer_base[L] + j * WL + i;
+      if (mask && !mask[pix]) continue; /* texel not requested */
       frag_t* f = &out[nout++];
-      f->pix = layer_base[L] + j * WL + i;
+      f->pix = pix;
       f->z = p->z;
       f->idx = idx;
       f->gamma = ((wx * wy) * p->iota[sel]) * alpha;
@@ -220,7 +223,8 @@ static void layer_bases(int W, int H, int nlayers, int64_t* base) {
 /* Steps 1-4 for one view: every fragment, sorted by (pixel, depth, index). */
 static frag_t* collect(int64_t n, const double* X, const double* Y, const double* Z,
                        const double* SW, const double* A, const cam_t* c, int nlayers,
-                       double eps, int fp32, int64_t* nfrag_out, proj_t** proj_out) {
+                       double eps, int fp32, const uint8_t* mask, int64_t* nfrag_out,
+                       proj_t** proj_out) {
   int64_t base[33];
   layer_bases(c->W, c->H, nlayers, base);
   proj_t* pr = (proj_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(proj_t));
@@ -232,7 +236,7 @@ static frag_t* collect(int64_t n, const double* X, const double* Y, const double
     if (!pr[p].valid) continue;
     double alpha = fp32 ? (double)(float)A[p] : A[p];
     for (int sel = 0; sel < pr[p].nl; ++sel)
-      nf = emit_layer(c, &pr[p], sel, p, alpha, fp32, base, fr, nf);
+      nf = emit_layer(c, &pr[p], sel, p, alpha, fp32, base, mask, fr, nf);
   }
   qsort(fr, (size_t)nf, sizeof(frag_t), frag_cmp);
   *nfrag_out = nf;
@@ -281,7 +285,7 @@ int64_t oracle_fragments(int64_t n, const double* X, const double* Y, const doub
   unpack_cam(cam, W, H, &c);
   int64_t nf = 0;
   proj_t* pr = NULL;
-  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, &nf, &pr);
+  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, NULL, &nf, &pr);
   if (!fr) return OR_ERR_MEM;
   for (int64_t k = 0; k < nf && k < cap; ++k) {
     const frag_t* f = &fr[k];
@@ -300,11 +304,12 @@ int64_t oracle_fragments(int64_t n, const double* X, const double* Y, const doub
 
 /* Forward, one view.  pyr: [sum_L H_L W_L][D] (layers concatenated, each row-major);
    counts: untruncated list length per texel; ids: [P][maxlist] kept point indices in
-   blend order, -1 padded. */
+   blend order, -1 padded.  mask (optional, [P] bytes): only texels with a non-zero
+   mask byte are evaluated; the others are left at 0 / -1. */
 int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z, const double* SW,
                    const double* A, const double* DESC, int D, const double* cam, int W, int H,
-                   int nlayers, int maxlist, double eps, int fp32, double* pyr, int32_t* counts,
-                   int64_t* ids) {
+                   int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
+                   double* pyr, int32_t* counts, int64_t* ids) {
   if (!check_args(n, D, W, H, nlayers, maxlist)) return OR_ERR_ARG;
   cam_t c;
   unpack_cam(cam, W, H, &c);
@@ -313,7 +318,7 @@ int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z,
   memset(counts, 0, (size_t)P * sizeof(int32_t));
   for (int64_t k = 0; k < P * maxlist; ++k) ids[k] = -1;
   int64_t nf = 0;
-  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, &nf, NULL);
+  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, mask, &nf, NULL);
   if (!fr) return OR_ERR_MEM;
   int64_t a = 0;
   while (a < nf) {
@@ -342,17 +347,20 @@ int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z,
 
 /* Backward, one view: gradients of sum(G * pyr) with respect to X, Y, Z, SW, A and DESC.
    Outputs are overwritten.  The depth order, culling and the 16-element clamp are
-   piecewise constant and carry no gradient; fragments beyond the clamp get none. */
+   piecewise constant and carry no gradient; fragments beyond the clamp get none.
+   mask (optional): only texels with a non-zero mask byte contribute, so a point's
+   gradient is exact when every texel it writes is in the mask. */
 int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z, const double* SW,
                     const double* A, const double* DESC, int D, const double* cam, int W, int H,
-                    int nlayers, int maxlist, double eps, int fp32, const double* G, double* gX,
-                    double* gY, double* gZ, double* gSW, double* gA, double* gDESC) {
+                    int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
+                    const double* G, double* gX, double* gY, double* gZ, double* gSW, double* gA,
+                    double* gDESC) {
   if (!check_args(n, D, W, H, nlayers, maxlist)) return OR_ERR_ARG;
   cam_t c;
   unpack_cam(cam, W, H, &c);
   int64_t nf = 0;
   proj_t* pr = NULL;
-  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, &nf, &pr);
+  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, mask, &nf, &pr);
   if (!fr) return OR_ERR_MEM;
   double* gxs = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* gys = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));

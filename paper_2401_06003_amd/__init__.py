@@ -1,0 +1,322 @@
+"""Trilinear point splatting (TRIPS, Sec. 3.1-3.2) on MI355X: thin Python binding.
+
+Every step of the renderer runs in the HIP kernels of libtrips.so behind the C ABI in
+include/trips.h; this module only marshals arguments.  PyTorch provides device memory
+and the stream.  If the library is not built, importing works but every call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrips.so")
+KEEP = 16
+MAX_VIEWS = 16
+
+c_float, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_float, ctypes.c_int32, ctypes.c_int64,
+                                                  ctypes.c_void_p, ctypes.c_size_t)
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("width", c_int32), ("height", c_int32),
+                ("znear", c_float)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("num_layers", c_int32), ("max_list", c_int32), ("eps", c_float),
+                ("desc_dim", c_int32)]
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("size_w", c_void_p),
+                ("opacity", c_void_p), ("desc", c_void_p), ("n", c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_w", c_int32), ("points_per_block", c_int32), ("item_entries", c_int32)]
+
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace or saved buffer too small",
+          -3: "capacity", -4: "HIP error", -5: "unsupported"}
+
+
+class TripsError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(status, "?"), status))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtrips.so; raises if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtrips.so is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.trips_layer_layout.argtypes = [P(Camera), P(Config), P(c_int32), P(c_int64)]
+        L.trips_buffer_sizes.argtypes = [P(Config), P(Camera), c_int32, c_int64, P(Tuning),
+                                         P(c_size_t), P(c_size_t)]
+        L.trips_forward.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_void_p,
+                                    c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]
+        L.trips_backward.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_void_p,
+                                     c_void_p, c_size_t, c_void_p, c_size_t] + [c_void_p] * 7
+        L.trips_export_fragments.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
+                                             c_size_t, c_void_p, c_void_p, c_void_p]
+        L.trips_forward_stats.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
+                                          c_size_t, P(c_int64), c_void_p]
+        L.trips_status_string.argtypes = [c_int32]
+        L.trips_status_string.restype = ctypes.c_char_p
+        L.trips_last_hip_error.restype = c_int32
+        L.trips_timing_enable.argtypes = [c_int32]
+        L.trips_timing_enable.restype = c_int32
+        L.trips_timing_read.argtypes = [P(c_float), P(c_int32)]
+        L.trips_timing_read.restype = c_int32
+        L.trips_stage_name.argtypes = [c_int32]
+        L.trips_stage_name.restype = ctypes.c_char_p
+        L.trips_plan_create.argtypes = ([P(Config), P(Points), P(Camera), c_int32, P(Tuning),
+                                         c_void_p, c_void_p, c_size_t, c_void_p, c_size_t]
+                                        + [c_void_p] * 8 + [P(c_void_p)])
+        L.trips_plan_launch.argtypes = [c_void_p, c_int32, c_void_p]
+        L.trips_plan_destroy.argtypes = [c_void_p]
+        for name in ("trips_layer_layout", "trips_buffer_sizes", "trips_forward", "trips_backward",
+                     "trips_export_fragments", "trips_forward_stats", "trips_plan_create",
+                     "trips_plan_launch"):
+            getattr(L, name).restype = c_int32
+        L.trips_plan_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status, what):
+    if status != 0:
+        raise TripsError(status, what)
+
+
+def make_camera(cam):
+    """Camera struct from a dict {R (9), t (3), fx, fy, cx, cy, W, H, znear}."""
+    c = Camera()
+    R = [float(v) for v in list(cam["R"]).__iter__()] if not hasattr(cam["R"], "reshape") else \
+        [float(v) for v in cam["R"].reshape(-1)]
+    t = [float(v) for v in (cam["t"].reshape(-1) if hasattr(cam["t"], "reshape") else cam["t"])]
+    c.R[:] = R
+    c.t[:] = t
+    c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    c.width, c.height = int(cam["W"]), int(cam["H"])
+    c.znear = float(cam.get("znear", 0.01))
+    return c
+
+
+def make_config(num_layers, desc_dim, eps=0.25, max_list=KEEP):
+    return Config(int(num_layers), int(max_list), float(eps), int(desc_dim))
+
+
+def make_tuning(tile_w=0, points_per_block=0, item_entries=0):
+    return Tuning(int(tile_w), int(points_per_block), int(item_entries))
+
+
+def layer_layout(cam, num_layers):
+    """[(W_L, H_L)] and texel offsets of one view."""
+    cfg = make_config(num_layers, 4)
+    dims = (c_int32 * (2 * num_layers))()
+    offs = (c_int64 * (num_layers + 1))()
+    _check(lib().trips_layer_layout(ctypes.byref(make_camera(cam)), ctypes.byref(cfg), dims, offs),
+           "trips_layer_layout")
+    return [(dims[2 * L], dims[2 * L + 1]) for L in range(num_layers)], list(offs)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _aligned_bytes(nbytes, device):
+    """A uint8 tensor of at least nbytes whose data pointer is 256-byte aligned."""
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(int(nbytes), 1)]
+
+
+class Renderer:
+    """Renders one or more views (different resolutions allowed) of a point cloud.
+
+    Owns the `saved` and `workspace` device buffers (torch tensors) sized by the library."""
+
+    def __init__(self, cams, num_layers, desc_dim, n_points, eps=0.25, tuning=None,
+                 device="cuda", share_buffers_with=None):
+        if isinstance(cams, dict):
+            cams = [cams]
+        if not 1 <= len(cams) <= MAX_VIEWS:
+            raise ValueError("1..%d views per renderer" % MAX_VIEWS)
+        self.cams_py = cams
+        self.V = len(cams)
+        self.cams = (Camera * self.V)(*[make_camera(c) for c in cams])
+        self.cfg = make_config(num_layers, desc_dim, eps)
+        self.tune = tuning if tuning is not None else make_tuning()
+        self.n = int(n_points)
+        self.D = int(desc_dim)
+        self.num_layers = int(num_layers)
+        ws, sv = c_size_t(), c_size_t()
+        _check(lib().trips_buffer_sizes(ctypes.byref(self.cfg), self.cams, self.V, self.n,
+                                        ctypes.byref(self.tune), ctypes.byref(ws), ctypes.byref(sv)),
+               "trips_buffer_sizes")
+        self.ws_bytes, self.saved_bytes = ws.value, sv.value
+        self.device = torch.device(device)
+        o = share_buffers_with
+        if o is not None and o.ws_bytes >= self.ws_bytes and o.saved_bytes >= self.saved_bytes:
+            # calls of the two renderers must not overlap on the device (same stream)
+            self.workspace, self.saved = o.workspace, o.saved
+            self.ws_bytes, self.saved_bytes = o.ws_bytes, o.saved_bytes
+        else:
+            self.workspace = _aligned_bytes(self.ws_bytes, self.device)
+            self.saved = _aligned_bytes(self.saved_bytes, self.device)
+        self.layouts = [layer_layout(c, num_layers) for c in cams]
+        self.view_texels = [lay[1][-1] for lay in self.layouts]
+        self.texels = sum(self.view_texels)
+
+    def pyramid_numel(self):
+        return self.texels * self.D
+
+    def _points(self, x, y, z, sw, alpha, desc):
+        for t in (x, y, z, sw, alpha, desc):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("point arrays must be contiguous float32 on %s" % self.device)
+        if x.numel() != self.n or desc.numel() != self.n * self.D:
+            raise ValueError("point count does not match the renderer")
+        return Points(x.data_ptr(), y.data_ptr(), z.data_ptr(), sw.data_ptr(), alpha.data_ptr(),
+                      desc.data_ptr(), self.n)
+
+    def forward(self, x, y, z, sw, alpha, desc, out=None):
+        """Flat float32 pyramid: views, then layers, each row-major [H_L][W_L][D]."""
+        pts = self._points(x, y, z, sw, alpha, desc)
+        if out is None:
+            out = torch.empty(self.pyramid_numel(), dtype=torch.float32, device=self.device)
+        _check(lib().trips_forward(ctypes.byref(self.cfg), ctypes.byref(pts), self.cams, self.V,
+                                   ctypes.byref(self.tune), _ptr(out), _ptr(self.saved),
+                                   self.saved_bytes, _ptr(self.workspace), self.ws_bytes, _stream()),
+               "trips_forward")
+        return out
+
+    def backward(self, x, y, z, sw, alpha, desc, grad_pyramid, outs=None):
+        """Gradients (x, y, z, sw, alpha, desc) of sum(grad_pyramid * pyramid)."""
+        pts = self._points(x, y, z, sw, alpha, desc)
+        g = grad_pyramid.contiguous()
+        if g.numel() != self.pyramid_numel() or g.dtype != torch.float32:
+            raise ValueError("grad_pyramid must be float32 with the pyramid's size")
+        if outs is None:
+            outs = [torch.empty(self.n, dtype=torch.float32, device=self.device) for _ in range(5)]
+            outs.append(torch.empty((self.n, self.D), dtype=torch.float32, device=self.device))
+        _check(lib().trips_backward(ctypes.byref(self.cfg), ctypes.byref(pts), self.cams, self.V,
+                                    ctypes.byref(self.tune), _ptr(g), _ptr(self.saved),
+                                    self.saved_bytes, _ptr(self.workspace), self.ws_bytes,
+                                    *[_ptr(o) for o in outs], _stream()),
+               "trips_backward")
+        return outs
+
+    def export_fragments(self):
+        """(counts [P] int32, ids [P, 16] int32) of the last forward call."""
+        counts = torch.empty(self.texels, dtype=torch.int32, device=self.device)
+        ids = torch.empty((self.texels, KEEP), dtype=torch.int32, device=self.device)
+        _check(lib().trips_export_fragments(ctypes.byref(self.cfg), self.cams, self.V,
+                                            ctypes.byref(self.tune), _ptr(self.saved),
+                                            self.saved_bytes, _ptr(counts), _ptr(ids), _stream()),
+               "trips_export_fragments")
+        return counts, ids
+
+    def stats(self):
+        """{'entries', 'items', 'bins', 'visible'} of the last forward call (synchronises)."""
+        st = (c_int64 * 4)()
+        _check(lib().trips_forward_stats(ctypes.byref(self.cfg), self.cams, self.V,
+                                         ctypes.byref(self.tune), _ptr(self.saved),
+                                         self.saved_bytes, st, _stream()), "trips_forward_stats")
+        return {"entries": st[0], "items": st[1], "bins": st[2], "visible": st[3]}
+
+    def split(self, flat):
+        """Per view, per layer [H_L, W_L, D] views of a flat pyramid."""
+        out, o = [], 0
+        for (dims, _offs) in self.layouts:
+            views = []
+            for (w, h) in dims:
+                views.append(flat[o:o + w * h * self.D].view(h, w, self.D))
+                o += w * h * self.D
+            out.append(views)
+        return out
+
+
+NUM_STAGES = 12
+
+
+def timing_enable(on=True):
+    """Bracket every kernel of later calls (this thread) with HIP events on its stream."""
+    _check(lib().trips_timing_enable(1 if on else 0), "trips_timing_enable")
+
+
+def timing_read():
+    """{stage: (milliseconds summed, launches)} since the last read; waits for the events."""
+    ms = (c_float * NUM_STAGES)()
+    n = (c_int32 * NUM_STAGES)()
+    _check(lib().trips_timing_read(ms, n), "trips_timing_read")
+    return {lib().trips_stage_name(k).decode(): (ms[k], n[k]) for k in range(NUM_STAGES)}
+
+
+class Plan:
+    """The batched form captured in a HIP graph: buffers bound once, replayed per launch."""
+
+    def __init__(self, renderer, x, y, z, sw, alpha, desc, pyramid, grad_pyramid=None,
+                 grads=None):
+        r = renderer
+        self.r = r
+        self.keep = (x, y, z, sw, alpha, desc, pyramid, grad_pyramid, grads)
+        pts = r._points(x, y, z, sw, alpha, desc)
+        g = grads if grads is not None else [None] * 6
+        h = c_void_p()
+        # capture on a stream of our own (the null stream cannot be captured)
+        cap = torch.cuda.Stream(device=r.device)
+        cap.wait_stream(torch.cuda.current_stream(r.device))
+        st = lib().trips_plan_create(ctypes.byref(r.cfg), ctypes.byref(pts), r.cams, r.V,
+                                     ctypes.byref(r.tune), _ptr(pyramid), _ptr(r.saved),
+                                     r.saved_bytes, _ptr(r.workspace), r.ws_bytes,
+                                     _ptr(grad_pyramid), *[_ptr(t) for t in g],
+                                     ctypes.c_void_p(cap.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise TripsError(st, "trips_plan_create (hip error %d)" % lib().trips_last_hip_error())
+        self.h = h
+
+    def launch(self, forward=True, backward=False):
+        which = (1 if forward else 0) | (2 if backward else 0)
+        _check(lib().trips_plan_launch(self.h, which, _stream()), "trips_plan_launch")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.trips_plan_destroy(self.h)
+            self.h = None
+
+
+class TripsSplat(torch.autograd.Function):
+    """Differentiable render: (x, y, z, sw, alpha, desc) -> flat pyramid."""
+
+    @staticmethod
+    def forward(ctx, x, y, z, sw, alpha, desc, renderer):
+        args = [t.detach().contiguous() for t in (x, y, z, sw, alpha, desc)]
+        out = renderer.forward(*args)
+        ctx.renderer = renderer
+        ctx.save_for_backward(*args)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        grads = ctx.renderer.backward(*ctx.saved_tensors, grad_out)
+        return tuple(grads) + (None,)
+
+
+def render(x, y, z, sw, alpha, desc, renderer):
+    """Flat pyramid of `renderer`'s views; differentiable in all six point arrays."""
+    return TripsSplat.apply(x, y, z, sw, alpha, desc, renderer)

@@ -1,0 +1,1422 @@
+// trips.hip -- HIP kernels and C ABI of the trilinear point-splatting renderer for gfx950.
+//
+// Method (TRIPS, Sec. 3.1-3.2, Eq. 1-7): every point is projected with a pinhole camera,
+// written with one trilinear write (a bilinear 2x2 footprint in each of the two pyramid
+// layers floor/ceil(log2 s)) and every (layer, texel) blends its 16 front-most fragments
+// front to back.  The backward pass is the analytic adjoint.
+//
+// Design for MI355X (no global atomics on the data path; random device atomics run at
+// ~27 G/s on this part, 1.3 G/s when contended, far below scattered stores):
+//   count      one workgroup per (point block, view): LDS histogram of tile entries
+//              (entry = one point's footprint part inside one 256-texel tile of one layer)
+//              -> one row of a per-block histogram matrix H[block][bin].
+//   colscan    per bin, exclusive prefix of H over blocks (in place) and bin totals.
+//   binscan    exclusive scans of bin totals -> bin starts, and of work items -> item starts.
+//   scatter    same blocks again: LDS ranks, entry written at bin_start + H + rank.
+//   fwd_items  persistent: one workgroup per work item (a bin, or a chunk of a heavy bin);
+//              entries -> fragments in LDS, counting sort by texel, per-texel top-16 kept
+//              in registers (thread = texel); blend, or write a partial top-16.
+//   fwd_merge  heavy bins: merge the partial top-16 lists, blend.
+//   bwd_pixels per texel: recompute T_m, reverse recurrence -> (dgamma_m, T_m gamma_m).
+//   bwd_items  per work item: every entry looks its corners up in the tile's kept lists
+//              (LDS) and writes one partial-gradient row per (view, slot, point).
+//   bwd_points per point: sum its rows, chain rule through the projection, write grads.
+// Every result is deterministic: ordering keys are unique (depth bits, point index) and
+// every sum is taken in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "trips.h"
+
+namespace {
+
+constexpr int KEEP = TRIPS_KEEP;
+constexpr int TP = 256;    // texels per tile == threads of a tile workgroup
+constexpr int NSLOT = 8;   // (layer entry 0/1) x (tile touch 0..3)
+constexpr int MAXV = TRIPS_MAX_VIEWS;
+constexpr int MAXL = TRIPS_MAX_LAYERS;
+constexpr uint64_t KEY_NONE = ~0ull;
+
+struct ViewP {
+  float R[9], t[3];
+  float fx, fy, cx, cy, znear;
+  int32_t W, H;
+  uint32_t bin_base, nbins;
+  uint32_t lbin[MAXL + 1];  // absolute first bin of each layer; [nl] = end of the view
+  uint32_t lout[MAXL];      // first texel of each layer in the pyramid of all views
+};
+
+struct Params {
+  int32_t V, nl, D, ltw;  // ltw = log2(tile width); tile height = 256 >> ltw
+  float eps;
+  uint32_t pb, nblk, NB, item_e;
+  int64_t n;
+  ViewP view[MAXV];
+};
+
+struct __align__(8) Entry {
+  uint32_t idx;    // point index
+  uint32_t zbits;  // bits of the camera depth (positive float: order preserving)
+  float u, v;      // layer-texel coordinates of the point, x / 2^L - 0.5
+  float ia;        // iota * alpha
+  uint32_t slot;   // layer entry (0/1) * 4 + tile touch (0..3)
+};
+static_assert(sizeof(Entry) == 24, "entry layout");
+
+// ------------------------------------------------------------------------------------
+// Geometry shared by every kernel that needs a point's footprint.  Compiled without
+// floating-point contraction: these operations decide integers (culling, layers,
+// texels, which corners exist) and must match any other correct single-precision
+// evaluation of the same sequence.
+
+__device__ __forceinline__ int layer_dim(int W, int L) { return (W + (1 << L) - 1) >> L; }
+__device__ __forceinline__ float pow2i(int e) { return __int_as_float((127 + e) << 23); }
+
+struct Geo {
+  float x, y, zc, s, qx, qy;  // screen x, y, depth, screen size, X_c/Z_c, Y_c/Z_c
+  int nl, L0;                 // number of layers (1 or 2) and the finer one
+  float io[2], dio[2];        // iota and d iota / d s per layer entry
+};
+
+__device__ bool project(const ViewP& c, float X, float Y, float Z, float sw, int nlayers,
+                        float eps, Geo& g) {
+  // Sec. 3.1, Eq. 2: pinhole projection and screen size s = f s_w / z
+  float Xc = __builtin_fmaf(c.R[0], X, __builtin_fmaf(c.R[1], Y, __builtin_fmaf(c.R[2], Z, c.t[0])));
+  float Yc = __builtin_fmaf(c.R[3], X, __builtin_fmaf(c.R[4], Y, __builtin_fmaf(c.R[5], Z, c.t[1])));
+  float Zc = __builtin_fmaf(c.R[6], X, __builtin_fmaf(c.R[7], Y, __builtin_fmaf(c.R[8], Z, c.t[2])));
+  if (!(Zc > c.znear)) return false;
+  float qx = Xc / Zc, qy = Yc / Zc;
+  float x = __builtin_fmaf(c.fx, qx, c.cx);
+  float y = __builtin_fmaf(c.fy, qy, c.cy);
+  float s = (c.fx * sw) / Zc;
+  if (!isfinite(x) || !isfinite(y) || !isfinite(s) || !(s > 0.0f)) return false;
+  g.x = x; g.y = y; g.zc = Zc; g.s = s; g.qx = qx; g.qy = qy;
+  // Sec. 3.1, Eq. 5: layers floor(log2 s) and ceil(log2 s) with linear layer weights
+  if (s < 1.0f) {
+    g.nl = 1; g.L0 = 0;
+    g.io[0] = __builtin_fmaf(1.0f - eps, s, eps);
+    g.dio[0] = 1.0f - eps;
+  } else if (s >= pow2i(nlayers - 1)) {
+    g.nl = 1; g.L0 = nlayers - 1; g.io[0] = 1.0f; g.dio[0] = 0.0f;
+  } else {
+    uint32_t b = __float_as_uint(s);
+    int e = int(b >> 23) - 127;                               // exact floor(log2 s), s normal
+    float t = __uint_as_float((b & 0x7fffffu) | (127u << 23));  // s / 2^e in [1, 2), exact
+    if (t == 1.0f) {
+      g.nl = 1; g.L0 = e; g.io[0] = 1.0f; g.dio[0] = 0.0f;
+    } else {
+      g.nl = 2; g.L0 = e;
+      g.io[0] = 2.0f - t; g.io[1] = t - 1.0f;  // exact (Sterbenz)
+      float inv = pow2i(-e);
+      g.dio[0] = -inv; g.dio[1] = inv;
+    }
+  }
+  return true;
+}
+
+struct Foot {
+  int i0, j0;       // texel of the lower-left corner
+  float fu, fv;     // fractional offsets inside the 2x2 footprint
+  float u, v;
+  uint32_t cmask;   // bit (2*dj + di) set if corner (i0+di, j0+dj) is written
+};
+
+// Sec. 3.1, Eq. 4: bilinear 2x2 footprint of a point in layer L (texel centres at
+// integer u, v in layer-texel units).  A corner is written iff it lies inside the layer
+// and both of its 1-D weights are non-zero.
+__device__ bool footprint(float x, float y, int L, int WL, int HL, Foot& f) {
+  float sc = pow2i(-L);
+  float u = x * sc - 0.5f;
+  float v = y * sc - 0.5f;
+  if (!(u > -1.0f && u < float(WL) && v > -1.0f && v < float(HL))) return false;
+  float flu = floorf(u), flv = floorf(v);
+  int i0 = int(flu), j0 = int(flv);
+  float fu = u - flu, fv = v - flv;
+  uint32_t m = 0;
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      int i = i0 + di, j = j0 + dj;
+      float wx = di ? fu : 1.0f - fu;
+      float wy = dj ? fv : 1.0f - fv;
+      bool in = (i >= 0) & (i < WL) & (j >= 0) & (j < HL) & (wx != 0.0f) & (wy != 0.0f);
+      m |= uint32_t(in) << (2 * dj + di);
+    }
+  f.i0 = i0; f.j0 = j0; f.fu = fu; f.fv = fv; f.u = u; f.v = v; f.cmask = m;
+  return m != 0;
+}
+
+// Corners of a footprint grouped by the 256-texel tile they fall in.  touch = dx + 2 dy
+// relative to the tile of corner (i0, j0) (floor division, so i0 = -1 is tile -1).
+__device__ __forceinline__ void touches(const Foot& f, int ltw, uint32_t (&tm)[4]) {
+  int lth = 8 - ltw;
+  int txb = f.i0 >> ltw, tyb = f.j0 >> lth;
+  int tc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    int di = c & 1, dj = c >> 1;
+    tc[c] = (((f.i0 + di) >> ltw) - txb) + 2 * (((f.j0 + dj) >> lth) - tyb);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m |= uint32_t(((f.cmask >> c) & 1u) && tc[c] == t) << c;
+    tm[t] = m;
+  }
+}
+
+// Decode a bin index into view, layer and tile coordinates (wave-uniform).
+struct BinInfo { int v, L, tx, ty, WL, HL; };
+__device__ BinInfo decode_bin(const Params& P, uint32_t b) {
+  BinInfo r;
+  int v = 0;
+  while (v + 1 < P.V && b >= P.view[v + 1].bin_base) ++v;
+  const ViewP& c = P.view[v];
+  int L = 0;
+  while (L + 1 < P.nl && b >= c.lbin[L + 1]) ++L;
+  r.v = v; r.L = L;
+  r.WL = layer_dim(c.W, L); r.HL = layer_dim(c.H, L);
+  int tiles_x = (r.WL + (1 << P.ltw) - 1) >> P.ltw;
+  int local = int(b - c.lbin[L]);
+  r.ty = local / tiles_x;
+  r.tx = local - r.ty * tiles_x;
+  return r;
+}
+
+// ------------------------------------------------------------------------------------
+// Wave and workgroup scans (wavefront of 64 lanes).
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan over a workgroup of NW waves; `ws` holds NW words of LDS.
+template <int NW>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* ws, uint32_t& total) {
+  uint32_t inc = wave_incl_scan(x);
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    uint32_t s = ws[k];
+    off += (k < w) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return off + inc - x;
+}
+
+// ------------------------------------------------------------------------------------
+// Per-texel top-16 in registers: keys ascending; insertion is a fixed compare network.
+
+__device__ __forceinline__ void top_insert(uint64_t (&k)[KEEP], float (&g)[KEEP], uint64_t nk,
+                                           float ng) {
+  if (!(nk < k[KEEP - 1])) return;
+#pragma unroll
+  for (int i = KEEP - 1; i > 0; --i) {
+    bool up = nk < k[i - 1];
+    uint64_t ki = up ? k[i - 1] : nk;
+    float gi = up ? g[i - 1] : ng;
+    bool here = nk < k[i];
+    k[i] = here ? ki : k[i];
+    g[i] = here ? gi : g[i];
+  }
+  if (nk < k[0]) { k[0] = nk; g[0] = ng; }
+}
+
+// ------------------------------------------------------------------------------------
+// Kernels.
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t value) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+// Emits every tile entry of one point for view c; calls f(bin, slot, sel, foot, geo).
+template <class F>
+__device__ __forceinline__ void for_each_entry(const Params& P, const ViewP& c, float X, float Y,
+                                               float Z, float sw, F&& f) {
+  Geo g;
+  if (!project(c, X, Y, Z, sw, P.nl, P.eps, g)) return;
+#pragma unroll
+  for (int sel = 0; sel < 2; ++sel) {
+    if (sel >= g.nl) break;
+    int L = g.L0 + sel;
+    int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
+    Foot ft;
+    if (!footprint(g.x, g.y, L, WL, HL, ft)) continue;
+    uint32_t tm[4];
+    touches(ft, P.ltw, tm);
+    int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
+    int txb = ft.i0 >> P.ltw, tyb = ft.j0 >> (8 - P.ltw);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (!tm[t]) continue;
+      int tx = txb + (t & 1), ty = tyb + (t >> 1);
+      uint32_t bin = c.lbin[L] + uint32_t(ty * tiles_x + tx);
+      f(bin, uint32_t(sel * 4 + t), sel, ft, g);
+    }
+  }
+}
+
+// count: LDS histogram (two 16-bit counters per word) of the entries of one point block
+// in one view; writes row `blk` of H for the bins of that view.
+__global__ __launch_bounds__(256) void k_count(const Params P, const float* __restrict__ X,
+                                               const float* __restrict__ Y,
+                                               const float* __restrict__ Z,
+                                               const float* __restrict__ SW,
+                                               uint32_t* __restrict__ H) {
+  extern __shared__ uint32_t hist[];
+  const int v = blockIdx.x % P.V;
+  const uint32_t blk = blockIdx.x / P.V;
+  const ViewP& c = P.view[v];
+  const uint32_t nw = (c.nbins + 1) >> 1;
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t p0 = int64_t(blk) * P.pb;
+  const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    for_each_entry(P, c, X[p], Y[p], Z[p], SW[p],
+                   [&](uint32_t bin, uint32_t, int, const Foot&, const Geo&) {
+                     uint32_t lb = bin - c.bin_base;
+                     atomicAdd(&hist[lb >> 1], 1u << ((lb & 1u) * 16u));
+                   });
+  }
+  __syncthreads();
+  uint32_t* row = H + size_t(blk) * P.NB + c.bin_base;
+  for (uint32_t i = threadIdx.x; i < c.nbins; i += blockDim.x)
+    row[i] = (hist[i >> 1] >> ((i & 1u) * 16u)) & 0xffffu;
+}
+
+// colscan: per bin, exclusive prefix of H over point blocks (in place) and the bin total.
+// Workgroup = 64 bins x 4 block segments.
+__global__ __launch_bounds__(256) void k_colscan(uint32_t* __restrict__ H, uint32_t* __restrict__ tot,
+                                                 uint32_t NB, uint32_t nblk) {
+  __shared__ uint32_t ssum[4][64];
+  const uint32_t lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const uint32_t b = blockIdx.x * 64 + lane;
+  const uint32_t per = (nblk + 3) / 4;
+  const uint32_t k0 = min(nblk, seg * per), k1 = min(nblk, k0 + per);
+  uint32_t sum = 0;
+  if (b < NB)
+    for (uint32_t k = k0; k < k1; ++k) sum += H[size_t(k) * NB + b];
+  ssum[seg][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0;
+  for (uint32_t s = 0; s < seg; ++s) run += ssum[s][lane];
+  if (b < NB) {
+    if (seg == 3) tot[b] = run + sum;
+    for (uint32_t k = k0; k < k1; ++k) {
+      size_t o = size_t(k) * NB + b;
+      uint32_t h = H[o];
+      H[o] = run;
+      run += h;
+    }
+  }
+}
+
+// binscan (one workgroup of 1024): bin_start = exclusive scan of totals; every bin is cut
+// into max(1, ceil(total / item_e)) work items; item_start = exclusive scan of those.
+__global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ tot,
+                                                  uint32_t* __restrict__ bin_start,
+                                                  uint32_t* __restrict__ item_start,
+                                                  uint32_t* __restrict__ info, uint32_t NB,
+                                                  uint32_t item_e) {
+  __shared__ uint32_t ws[16];
+  uint32_t carry_e = 0, carry_i = 0;
+  for (uint32_t base = 0; base < NB; base += 4096) {
+    uint32_t e[4], it[4], se = 0, si = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t idx = base + threadIdx.x * 4 + k;
+      e[k] = idx < NB ? tot[idx] : 0u;
+      it[k] = idx < NB ? max(1u, (e[k] + item_e - 1) / item_e) : 0u;
+      se += e[k];
+      si += it[k];
+    }
+    uint32_t te, ti;
+    uint32_t oe = block_excl_scan<16>(se, ws, te);
+    uint32_t oi = block_excl_scan<16>(si, ws, ti);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t idx = base + threadIdx.x * 4 + k;
+      if (idx < NB) {
+        bin_start[idx] = carry_e + oe;
+        item_start[idx] = carry_i + oi;
+      }
+      oe += e[k];
+      oi += it[k];
+    }
+    carry_e += te;
+    carry_i += ti;
+  }
+  if (threadIdx.x == 0) {
+    bin_start[NB] = carry_e;
+    item_start[NB] = carry_i;
+    info[0] = carry_e;
+    info[1] = carry_i;
+    info[2] = 0;  // visible (point, view) pairs, accumulated by the scatter pass
+  }
+}
+
+// scatter: the count pass again, with LDS ranks; entry -> bin_start + H (column prefix) + rank.
+__global__ __launch_bounds__(256) void k_scatter(const Params P, const float* __restrict__ X,
+                                                 const float* __restrict__ Y,
+                                                 const float* __restrict__ Z,
+                                                 const float* __restrict__ SW,
+                                                 const float* __restrict__ A,
+                                                 const uint32_t* __restrict__ H,
+                                                 const uint32_t* __restrict__ bin_start,
+                                                 Entry* __restrict__ ent,
+                                                 uint32_t* __restrict__ info) {
+  extern __shared__ uint32_t hist[];
+  __shared__ uint32_t s_vis;
+  if (threadIdx.x == 0) s_vis = 0;
+  const int v = blockIdx.x % P.V;
+  const uint32_t blk = blockIdx.x / P.V;
+  const ViewP& c = P.view[v];
+  const uint32_t nw = (c.nbins + 1) >> 1;
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const uint32_t* row = H + size_t(blk) * P.NB;
+  const int64_t p0 = int64_t(blk) * P.pb;
+  const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
+  uint32_t vis = 0;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const float alpha = A[p];
+    bool any = false;
+    for_each_entry(P, c, X[p], Y[p], Z[p], SW[p],
+                   [&](uint32_t bin, uint32_t slot, int sel, const Foot& ft, const Geo& g) {
+                     any = true;
+                     uint32_t lb = bin - c.bin_base;
+                     uint32_t sh = (lb & 1u) * 16u;
+                     uint32_t old = atomicAdd(&hist[lb >> 1], 1u << sh);
+                     uint32_t rank = (old >> sh) & 0xffffu;
+                     uint32_t dst = bin_start[bin] + row[bin] + rank;
+                     Entry e;
+                     e.idx = uint32_t(p);
+                     e.zbits = __float_as_uint(g.zc);
+                     e.u = ft.u;
+                     e.v = ft.v;
+                     e.ia = g.io[sel] * alpha;
+                     e.slot = slot;
+                     ent[dst] = e;
+                   });
+    vis += any ? 1u : 0u;
+  }
+  // number of (point, view) pairs with at least one entry, for reports
+  atomicAdd(&s_vis, vis);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&info[2], s_vis);
+}
+
+// Corners of entry e that lie in tile (tx, ty): corner c = 2 dj + di is present iff bit c
+// of the returned mask is set; cs[c] then holds its local texel id and weights.
+struct Corner { int p; float wx, wy; float sx, sy; };
+__device__ __forceinline__ uint32_t entry_corners(const Entry& e, const BinInfo& bi, int ltw,
+                                                  Corner (&cs)[4]) {
+  const int lth = 8 - ltw;
+  float flu = floorf(e.u), flv = floorf(e.v);
+  int i0 = int(flu), j0 = int(flv);
+  float fu = e.u - flu, fv = e.v - flv;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      const int c = 2 * dj + di;
+      int i = i0 + di, j = j0 + dj;
+      float wx = di ? fu : 1.0f - fu;
+      float wy = dj ? fv : 1.0f - fv;
+      bool in = (i >= 0) & (i < bi.WL) & (j >= 0) & (j < bi.HL) & (wx != 0.0f) & (wy != 0.0f) &
+                ((i >> ltw) == bi.tx) & ((j >> lth) == bi.ty);
+      cs[c].p = ((j - (bi.ty << lth)) << ltw) + (i - (bi.tx << ltw));
+      cs[c].wx = wx; cs[c].wy = wy;
+      cs[c].sx = di ? 1.0f : -1.0f; cs[c].sy = dj ? 1.0f : -1.0f;
+      mask |= uint32_t(in) << c;
+    }
+  return mask;
+}
+
+__device__ __forceinline__ uint32_t find_item_bin(const uint32_t* __restrict__ item_start,
+                                                  uint32_t NB, uint32_t it) {
+  // largest b with item_start[b] <= it (item_start is non-decreasing, every bin >= 1 item)
+  uint32_t lo = 0, hi = NB;  // invariant: item_start[lo] <= it < item_start[hi]
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (item_start[mid] <= it) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Blend the kept fragments of one texel front to back (Eq. 6-7) and write its outputs.
+template <int D>
+__device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& bi, uint32_t b,
+                                               const uint64_t (&kk)[KEEP], const float (&kg)[KEEP],
+                                               uint32_t n, const float* __restrict__ desc,
+                                               float* __restrict__ pyr, uint32_t* __restrict__ npix,
+                                               uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
+  const int t = threadIdx.x;
+  const int lth = 8 - P.ltw;
+  const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int j = (bi.ty << lth) + (t >> P.ltw);
+  const uint32_t k = min(n, uint32_t(KEEP));
+  float C[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) C[d] = 0.0f;
+  float T = 1.0f;
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    if (uint32_t(m) < k) {
+      const uint32_t idx = uint32_t(kk[m]);
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx) * D);
+      const float w = T * kg[m];
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q) {
+        float4 tv = tp[q];
+        C[4 * q + 0] += w * tv.x;
+        C[4 * q + 1] += w * tv.y;
+        C[4 * q + 2] += w * tv.z;
+        C[4 * q + 3] += w * tv.w;
+      }
+      T = T * (1.0f - kg[m]);
+    }
+  }
+  if (i < bi.WL && j < bi.HL) {
+    const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+    float4* op = reinterpret_cast<float4*>(pyr + o);
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q) op[q] = make_float4(C[4 * q], C[4 * q + 1], C[4 * q + 2], C[4 * q + 3]);
+  }
+  npix[size_t(b) * TP + t] = n;
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m)
+    if (uint32_t(m) < k) {
+      kkey[(size_t(b) * KEEP + m) * TP + t] = kk[m];
+      kgam[(size_t(b) * KEEP + m) * TP + t] = kg[m];
+    }
+}
+
+constexpr int SUB_E = 256;            // entries per LDS round (one per thread)
+constexpr int SUB_F = 4 * SUB_E;      // fragments per LDS round (at most 4 per entry)
+
+// fwd_items: persistent; one workgroup per work item, coarse layers first.
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_items(
+    const Params P, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ item_start,
+    const Entry* __restrict__ ent, const float* __restrict__ desc, uint32_t* __restrict__ ctr,
+    float* __restrict__ pyr, uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey,
+    float* __restrict__ kgam, uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey,
+    float* __restrict__ pgam) {
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t hist[TP];
+  __shared__ uint32_t ws[4];
+  __shared__ uint64_t skey[SUB_F];
+  __shared__ float sgam[SUB_F];
+  const int t = threadIdx.x;
+  const uint32_t total = item_start[P.NB];
+  for (;;) {
+    if (t == 0) s_item = atomicAdd(&ctr[0], 1u);
+    __syncthreads();
+    const uint32_t got = s_item;
+    __syncthreads();
+    if (got >= total) break;
+    const uint32_t it = total - 1 - got;
+    const uint32_t b = find_item_bin(item_start, P.NB, it);
+    const BinInfo bi = decode_bin(P, b);
+    const uint32_t nitems = item_start[b + 1] - item_start[b];
+    const uint32_t e0 = bin_start[b] + (it - item_start[b]) * P.item_e;
+    const uint32_t e1 = min(e0 + P.item_e, bin_start[b + 1]);
+    uint64_t kk[KEEP];
+    float kg[KEEP];
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
+    uint32_t n = 0;
+    for (uint32_t s0 = e0; s0 < e1; s0 += SUB_E) {
+      hist[t] = 0;
+      __syncthreads();
+      Corner cs[4];
+      uint32_t cm = 0;
+      uint64_t key = 0;
+      float ia = 0.0f;
+      uint32_t rank[4] = {0, 0, 0, 0};
+      if (s0 + t < e1) {
+        const Entry e = ent[s0 + t];
+        cm = entry_corners(e, bi, P.ltw, cs);
+        key = (uint64_t(e.zbits) << 32) | e.idx;
+        ia = e.ia;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if ((cm >> q) & 1u) rank[q] = atomicAdd(&hist[cs[q].p], 1u);
+      }
+      __syncthreads();
+      uint32_t cnt = hist[t], tot;
+      uint32_t base = block_excl_scan<4>(cnt, ws, tot);
+      __syncthreads();
+      hist[t] = base;  // reuse as the start of texel t's run
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((cm >> q) & 1u) {
+          uint32_t o = hist[cs[q].p] + rank[q];
+          skey[o] = key;
+          sgam[o] = (cs[q].wx * cs[q].wy) * ia;
+        }
+      __syncthreads();
+      for (uint32_t r = 0; r < cnt; ++r) top_insert(kk, kg, skey[base + r], sgam[base + r]);
+      n += cnt;
+      __syncthreads();
+    }
+    if (nitems == 1) {
+      finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam);
+    } else {
+      pcnt[size_t(it) * TP + t] = n;
+      const uint32_t k = min(n, uint32_t(KEEP));
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m)
+        if (uint32_t(m) < k) {
+          pkey[(size_t(it) * KEEP + m) * TP + t] = kk[m];
+          pgam[(size_t(it) * KEEP + m) * TP + t] = kg[m];
+        }
+    }
+  }
+}
+
+// fwd_merge: bins that were cut into several items merge their partial top-16 lists.
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_merge(
+    const Params P, const uint32_t* __restrict__ item_start, const uint32_t* __restrict__ pcnt,
+    const uint64_t* __restrict__ pkey, const float* __restrict__ pgam,
+    const float* __restrict__ desc, float* __restrict__ pyr, uint32_t* __restrict__ npix,
+    uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
+  const int t = threadIdx.x;
+  for (uint32_t b = blockIdx.x; b < P.NB; b += gridDim.x) {
+    const uint32_t i0 = item_start[b], i1 = item_start[b + 1];
+    if (i1 - i0 <= 1) continue;
+    const BinInfo bi = decode_bin(P, b);
+    uint64_t kk[KEEP];
+    float kg[KEEP];
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
+    uint32_t n = 0;
+    for (uint32_t it = i0; it < i1; ++it) {
+      const uint32_t c = pcnt[size_t(it) * TP + t];
+      n += c;
+      const uint32_t k = min(c, uint32_t(KEEP));
+      for (uint32_t m = 0; m < k; ++m) {
+        const uint64_t key = pkey[(size_t(it) * KEEP + m) * TP + t];
+        if (!(key < kk[KEEP - 1])) break;  // partial lists are sorted
+        top_insert(kk, kg, key, pgam[(size_t(it) * KEEP + m) * TP + t]);
+      }
+    }
+    finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam);
+  }
+}
+
+// export: counts and kept ids in pyramid texel order.
+__global__ __launch_bounds__(256) void k_export(const Params P, const uint32_t* __restrict__ npix,
+                                                const uint64_t* __restrict__ kkey,
+                                                int32_t* __restrict__ counts,
+                                                int32_t* __restrict__ ids) {
+  const uint32_t b = blockIdx.x;
+  const int t = threadIdx.x;
+  const BinInfo bi = decode_bin(P, b);
+  const int lth = 8 - P.ltw;
+  const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int j = (bi.ty << lth) + (t >> P.ltw);
+  if (i >= bi.WL || j >= bi.HL) return;
+  const size_t o = size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i;
+  const uint32_t n = npix[size_t(b) * TP + t];
+  counts[o] = int32_t(n);
+  for (int m = 0; m < KEEP; ++m)
+    ids[o * KEEP + m] = uint32_t(m) < n ? int32_t(uint32_t(kkey[(size_t(b) * KEEP + m) * TP + t])) : -1;
+}
+
+// bwd_pixels: per texel, recompute transmittance T_m front to back and run the reverse
+// recurrence B_{m-1} = gamma_m g_m + (1 - gamma_m) B_m (g_m = G . tau_m, B_last = 0):
+// dL/dgamma_m = T_m (g_m - B_m); the descriptor gets T_m gamma_m G.
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32_t* __restrict__ npix,
+                                                    const uint64_t* __restrict__ kkey,
+                                                    const float* __restrict__ kgam,
+                                                    const float* __restrict__ desc,
+                                                    const float* __restrict__ gpyr,
+                                                    float2* __restrict__ bst) {
+  const uint32_t b = blockIdx.x;
+  const int t = threadIdx.x;
+  const uint32_t n = npix[size_t(b) * TP + t];
+  if (n == 0) return;
+  const BinInfo bi = decode_bin(P, b);
+  const int lth = 8 - P.ltw;
+  const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int j = (bi.ty << lth) + (t >> P.ltw);
+  const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+  float G[D];
+  const float4* gp = reinterpret_cast<const float4*>(gpyr + o);
+#pragma unroll
+  for (int q = 0; q < D / 4; ++q) {
+    float4 gv = gp[q];
+    G[4 * q] = gv.x; G[4 * q + 1] = gv.y; G[4 * q + 2] = gv.z; G[4 * q + 3] = gv.w;
+  }
+  const uint32_t k = min(n, uint32_t(KEEP));
+  float gam[KEEP], Tm[KEEP], gm[KEEP];
+  float T = 1.0f;
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    gam[m] = 0.0f; Tm[m] = 0.0f; gm[m] = 0.0f;
+    if (uint32_t(m) < k) {
+      const size_t ko = (size_t(b) * KEEP + m) * TP + t;
+      const uint32_t idx = uint32_t(kkey[ko]);
+      gam[m] = kgam[ko];
+      Tm[m] = T;
+      T = T * (1.0f - gam[m]);
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx) * D);
+      float acc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q) {
+        float4 tv = tp[q];
+        acc += G[4 * q] * tv.x + G[4 * q + 1] * tv.y + G[4 * q + 2] * tv.z + G[4 * q + 3] * tv.w;
+      }
+      gm[m] = acc;
+    }
+  }
+  float B = 0.0f;
+#pragma unroll
+  for (int m = KEEP - 1; m >= 0; --m) {
+    if (uint32_t(m) < k) {
+      const float dgam = Tm[m] * (gm[m] - B);
+      B = gam[m] * gm[m] + (1.0f - gam[m]) * B;
+      bst[(size_t(b) * KEEP + m) * TP + t] = make_float2(dgam, Tm[m] * gam[m]);
+    }
+  }
+}
+
+// bwd_items: per work item, each entry finds its corners in the tile's kept lists and writes
+// its partial-gradient row: (A, Bx, By, 0, tau[D]) with A = sum dgamma wx wy,
+// Bx = sum dgamma sx wy, By = sum dgamma wx sy, tau = sum T_m gamma_m G over its corners.
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_items(
+    const Params P, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ item_start,
+    const Entry* __restrict__ ent, const uint32_t* __restrict__ npix,
+    const uint64_t* __restrict__ kkey, const float2* __restrict__ bst,
+    const float* __restrict__ gpyr, uint32_t* __restrict__ ctr, float* __restrict__ rows) {
+  constexpr int RW = 4 + D;
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_k[TP];
+  __shared__ uint64_t s_key[KEEP][TP];
+  __shared__ float2 s_bst[KEEP][TP];
+  __shared__ float s_G[TP][D + 1];
+  const int t = threadIdx.x;
+  const uint32_t total = item_start[P.NB];
+  uint32_t loaded = ~0u;
+  for (;;) {
+    if (t == 0) s_item = atomicAdd(&ctr[1], 1u);
+    __syncthreads();
+    const uint32_t got = s_item;
+    __syncthreads();
+    if (got >= total) break;
+    const uint32_t it = total - 1 - got;
+    const uint32_t b = find_item_bin(item_start, P.NB, it);
+    const BinInfo bi = decode_bin(P, b);
+    const int lth = 8 - P.ltw;
+    if (b != loaded) {  // stage the tile's kept lists, blend adjoints and upstream gradient
+      const uint32_t n = npix[size_t(b) * TP + t];
+      const uint32_t k = min(n, uint32_t(KEEP));
+      s_k[t] = k;
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) {
+        if (uint32_t(m) < k) {
+          s_key[m][t] = kkey[(size_t(b) * KEEP + m) * TP + t];
+          s_bst[m][t] = bst[(size_t(b) * KEEP + m) * TP + t];
+        } else {
+          s_key[m][t] = KEY_NONE;
+        }
+      }
+      const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+      const int j = (bi.ty << lth) + (t >> P.ltw);
+      if (i < bi.WL && j < bi.HL && k > 0) {
+        const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
+      } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) s_G[t][d] = 0.0f;
+      }
+      loaded = b;
+      __syncthreads();
+    }
+    const uint32_t e0 = bin_start[b] + (it - item_start[b]) * P.item_e;
+    const uint32_t e1 = min(e0 + P.item_e, bin_start[b + 1]);
+    for (uint32_t e = e0 + t; e < e1; e += TP) {
+      const Entry en = ent[e];
+      Corner cs[4];
+      const uint32_t cm = entry_corners(en, bi, P.ltw, cs);
+      const uint64_t key = (uint64_t(en.zbits) << 32) | en.idx;
+      float A = 0.0f, Bx = 0.0f, By = 0.0f;
+      float tau[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) tau[d] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!((cm >> q) & 1u)) continue;
+        const int p = cs[q].p;
+        const uint32_t kp = s_k[p];
+        if (kp == 0 || key > s_key[kp - 1][p]) continue;  // not among the kept fragments
+        uint32_t m = 0;
+        while (m < kp && s_key[m][p] != key) ++m;
+        if (m == kp) continue;
+        const float2 st = s_bst[m][p];
+        const float dg = st.x;
+        A += dg * (cs[q].wx * cs[q].wy);
+        Bx += dg * (cs[q].sx * cs[q].wy);
+        By += dg * (cs[q].wx * cs[q].sy);
+#pragma unroll
+        for (int d = 0; d < D; ++d) tau[d] += st.y * s_G[p][d];
+      }
+      float* r = rows + ((size_t(bi.v) * NSLOT + en.slot) * size_t(P.n) + en.idx) * RW;
+      float4* r4 = reinterpret_cast<float4*>(r);
+      r4[0] = make_float4(A, Bx, By, 0.0f);
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q)
+        r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
+    }
+    __syncthreads();  // the next item may restage the tables
+  }
+}
+
+// bwd_points: per point, every view: read the rows of its entries, apply the layer and
+// footprint factors, then the chain rule through the projection; sum over views.
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_points(
+    const Params P, const float* __restrict__ X, const float* __restrict__ Y,
+    const float* __restrict__ Z, const float* __restrict__ SW, const float* __restrict__ A,
+    const float* __restrict__ rows, float* __restrict__ gX, float* __restrict__ gY,
+    float* __restrict__ gZ, float* __restrict__ gSW, float* __restrict__ gA,
+    float* __restrict__ gD) {
+  constexpr int RW = 4 + D;
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P.n) return;
+  const float x = X[p], y = Y[p], z = Z[p], sw = SW[p], alpha = A[p];
+  float ax = 0.f, ay = 0.f, az = 0.f, asw = 0.f, aal = 0.f;
+  float at[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) at[d] = 0.0f;
+  for (int v = 0; v < P.V; ++v) {
+    const ViewP& c = P.view[v];
+    Geo g;
+    if (!project(c, x, y, z, sw, P.nl, P.eps, g)) continue;
+    float gxs = 0.f, gys = 0.f, gs = 0.f, gal = 0.f;
+    float gt[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) gt[d] = 0.0f;
+#pragma unroll
+    for (int sel = 0; sel < 2; ++sel) {
+      if (sel >= g.nl) break;
+      const int L = g.L0 + sel;
+      const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
+      Foot ft;
+      if (!footprint(g.x, g.y, L, WL, HL, ft)) continue;
+      uint32_t tm[4];
+      touches(ft, P.ltw, tm);
+      float sA = 0.f, sBx = 0.f, sBy = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!tm[q]) continue;
+        const float4* r4 = reinterpret_cast<const float4*>(
+            rows + ((size_t(v) * NSLOT + sel * 4 + q) * size_t(P.n) + p) * RW);
+        const float4 h = r4[0];
+        sA += h.x; sBx += h.y; sBy += h.z;
+#pragma unroll
+        for (int qq = 0; qq < D / 4; ++qq) {
+          const float4 tv = r4[1 + qq];
+          gt[4 * qq] += tv.x; gt[4 * qq + 1] += tv.y; gt[4 * qq + 2] += tv.z; gt[4 * qq + 3] += tv.w;
+        }
+      }
+      const float io = g.io[sel];
+      const float sc = pow2i(-L);
+      gal += sA * io;
+      gs += sA * alpha * g.dio[sel];
+      gxs += sBx * io * alpha * sc;
+      gys += sBy * io * alpha * sc;
+    }
+    // chain rule: x = fx Xc/Zc + cx, y = fy Yc/Zc + cy, s = fx sw / Zc
+    const float iz = 1.0f / g.zc;
+    const float dXc = gxs * c.fx * iz;
+    const float dYc = gys * c.fy * iz;
+    const float dZc = -(gxs * c.fx * g.qx + gys * c.fy * g.qy + gs * g.s) * iz;
+    ax += c.R[0] * dXc + c.R[3] * dYc + c.R[6] * dZc;
+    ay += c.R[1] * dXc + c.R[4] * dYc + c.R[7] * dZc;
+    az += c.R[2] * dXc + c.R[5] * dYc + c.R[8] * dZc;
+    asw += gs * c.fx * iz;
+    // per-view sums first, then across views, so a batched call equals the sum of
+    // single-view calls bit for bit
+    aal += gal;
+#pragma unroll
+    for (int d = 0; d < D; ++d) at[d] += gt[d];
+  }
+  gX[p] = ax; gY[p] = ay; gZ[p] = az; gSW[p] = asw; gA[p] = aal;
+  float4* gd4 = reinterpret_cast<float4*>(gD + size_t(p) * D);
+#pragma unroll
+  for (int q = 0; q < D / 4; ++q) gd4[q] = make_float4(at[4 * q], at[4 * q + 1], at[4 * q + 2], at[4 * q + 3]);
+}
+
+// ------------------------------------------------------------------------------------
+// Host side.
+
+thread_local int32_t g_last_hip = 0;
+
+// Optional per-kernel timing (reports only): a start and an end event around every kernel
+// launch, on the launch stream; read back and summed per stage by trips_timing_read.
+enum Stage { ST_FILL_F, ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_SCATTER, ST_FWD_ITEMS, ST_FWD_MERGE,
+             ST_FILL_B, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_POINTS, ST_EXPORT, NUM_STAGES };
+const char* const kStageNames[NUM_STAGES] = {
+    "fill_fwd", "count", "colscan", "binscan", "scatter", "fwd_items", "fwd_merge",
+    "fill_bwd", "bwd_pixels", "bwd_items", "bwd_points", "export"};
+static_assert(NUM_STAGES == TRIPS_NUM_STAGES, "stage table");
+
+struct TimingState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // pairs: start, end
+  std::vector<int> stage;        // stage of each recorded pair
+  size_t used = 0;               // pairs recorded since the last read
+};
+thread_local TimingState g_timing;
+
+// Wraps one kernel launch: records events around it when timing is enabled and the stream
+// is not being captured into a graph.
+struct StageTimer {
+  hipStream_t st;
+  int pair = -1;
+  StageTimer(int stage, hipStream_t s) : st(s) {
+    if (!g_timing.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    TimingState& t = g_timing;
+    if (t.used * 2 + 2 > t.pool.size()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+      t.pool.push_back(a);
+      t.pool.push_back(b);
+      t.stage.push_back(0);
+    }
+    pair = int(t.used++);
+    t.stage[pair] = stage;
+    (void)hipEventRecord(t.pool[2 * pair], s);
+  }
+  ~StageTimer() {
+    if (pair >= 0) (void)hipEventRecord(g_timing.pool[2 * pair + 1], st);
+  }
+};
+
+struct Layout {
+  Params P;
+  uint32_t nbv_max;   // largest bin count of one view (LDS histogram size)
+  uint64_t ecap;      // entry capacity
+  uint64_t icap;      // work-item capacity
+  uint64_t npyr;      // texels of all views and layers
+  // saved buffer
+  size_t s_info, s_bin_start, s_item_start, s_npix, s_kkey, s_kgam, s_ent, saved_bytes;
+  // workspace
+  size_t w_ctr, w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, ws_bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int32_t views,
+                         int64_t n, const trips_tuning* tun, Layout& lay) {
+  if (!cfg || !cams) return TRIPS_ERR_INVALID_ARG;
+  if (views < 1 || views > MAXV || n < 0) return TRIPS_ERR_INVALID_ARG;
+  if (cfg->num_layers < 1 || cfg->num_layers > MAXL) return TRIPS_ERR_INVALID_ARG;
+  if (!(cfg->eps >= 0.0f && cfg->eps <= 1.0f)) return TRIPS_ERR_INVALID_ARG;
+  if (cfg->desc_dim < 1 || cfg->max_list < 1) return TRIPS_ERR_INVALID_ARG;
+  if (cfg->max_list != KEEP) return TRIPS_ERR_UNSUPPORTED;
+  if (cfg->desc_dim != 4 && cfg->desc_dim != 8) return TRIPS_ERR_UNSUPPORTED;
+  int tile_w = 16, pb = 4096, item_e = 4096;
+  if (tun) {
+    if (tun->tile_w) tile_w = tun->tile_w;
+    if (tun->points_per_block) pb = tun->points_per_block;
+    if (tun->item_entries) item_e = tun->item_entries;
+  }
+  int ltw = 0;
+  while ((1 << ltw) < tile_w) ++ltw;
+  if ((1 << ltw) != tile_w || ltw < 3 || ltw > 6) return TRIPS_ERR_INVALID_ARG;
+  if (pb < 256 || pb > 65535 || item_e < 256 || item_e > 65536) return TRIPS_ERR_INVALID_ARG;
+  std::memset(&lay, 0, sizeof(lay));
+  Params& P = lay.P;
+  P.V = views; P.nl = cfg->num_layers; P.D = cfg->desc_dim; P.ltw = ltw; P.eps = cfg->eps;
+  P.pb = uint32_t(pb); P.item_e = uint32_t(item_e); P.n = n;
+  P.nblk = uint32_t((n + pb - 1) / pb);
+  const int lth = 8 - ltw;
+  uint64_t bins = 0, texels = 0;
+  lay.nbv_max = 0;
+  for (int v = 0; v < views; ++v) {
+    const trips_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > (1 << 16) || c.height > (1 << 16))
+      return TRIPS_ERR_INVALID_ARG;
+    if (!(c.znear > 0.0f) || !std::isfinite(c.znear)) return TRIPS_ERR_INVALID_ARG;
+    for (int k = 0; k < 9; ++k) if (!std::isfinite(c.R[k])) return TRIPS_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) if (!std::isfinite(c.t[k])) return TRIPS_ERR_INVALID_ARG;
+    if (!std::isfinite(c.fx) || !std::isfinite(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return TRIPS_ERR_INVALID_ARG;
+    ViewP& vp = P.view[v];
+    std::memcpy(vp.R, c.R, sizeof(vp.R));
+    std::memcpy(vp.t, c.t, sizeof(vp.t));
+    vp.fx = c.fx; vp.fy = c.fy; vp.cx = c.cx; vp.cy = c.cy; vp.znear = c.znear;
+    vp.W = c.width; vp.H = c.height;
+    vp.bin_base = uint32_t(bins);
+    uint64_t vb = 0;
+    for (int L = 0; L < P.nl; ++L) {
+      const uint64_t WL = (uint64_t(c.width) + (1ull << L) - 1) >> L;
+      const uint64_t HL = (uint64_t(c.height) + (1ull << L) - 1) >> L;
+      const uint64_t tx = (WL + (1ull << ltw) - 1) >> ltw;
+      const uint64_t ty = (HL + (1ull << lth) - 1) >> lth;
+      vp.lbin[L] = uint32_t(bins + vb);
+      vp.lout[L] = uint32_t(texels);
+      vb += tx * ty;
+      texels += WL * HL;
+    }
+    vp.lbin[P.nl] = uint32_t(bins + vb);
+    vp.nbins = uint32_t(vb);
+    bins += vb;
+    if (vb > 32768) return TRIPS_ERR_UNSUPPORTED;  // LDS histogram of one view (64 KB)
+    lay.nbv_max = std::max<uint32_t>(lay.nbv_max, uint32_t(vb));
+    if (bins >= (1ull << 31) / TP || texels >= (1ull << 32)) return TRIPS_ERR_CAPACITY;
+  }
+  P.NB = uint32_t(bins);
+  lay.npyr = texels;
+  lay.ecap = 8ull * uint64_t(n) * uint64_t(views);  // <= 2 layers x 4 tiles per point and view
+  if (lay.ecap >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
+  lay.icap = bins + (lay.ecap + item_e - 1) / item_e;
+  if (lay.icap >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
+  const size_t NB = bins;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  lay.s_info = take(64 * 4);
+  lay.s_bin_start = take((NB + 1) * 4);
+  lay.s_item_start = take((NB + 1) * 4);
+  lay.s_npix = take(NB * TP * 4);
+  lay.s_kkey = take(NB * TP * KEEP * 8);
+  lay.s_kgam = take(NB * TP * KEEP * 4);
+  lay.s_ent = take(size_t(lay.ecap) * sizeof(Entry));
+  lay.saved_bytes = o;
+  o = 0;
+  lay.w_ctr = take(64 * 4);
+  const size_t scratch = o;
+  // forward scratch
+  lay.w_H = take(size_t(P.nblk) * NB * 4);
+  lay.w_tot = take(NB * 4);
+  lay.w_pcnt = take(size_t(lay.icap) * TP * 4);
+  lay.w_pkey = take(size_t(lay.icap) * TP * KEEP * 8);
+  lay.w_pgam = take(size_t(lay.icap) * TP * KEEP * 4);
+  const size_t fwd_end = o;
+  // backward scratch reuses the same bytes
+  o = scratch;
+  lay.w_bst = take(NB * TP * KEEP * sizeof(float2));
+  lay.w_rows = take(size_t(views) * NSLOT * size_t(n) * (4 + P.D) * 4);
+  lay.ws_bytes = std::max(fwd_end, o);
+  return TRIPS_OK;
+}
+
+#define TRIPS_HIP(call)                                        \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) { g_last_hip = int32_t(e_); return TRIPS_ERR_HIP; } \
+  } while (0)
+
+int persistent_grid() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus * 8;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+trips_status check_points(const trips_points* pts, const Layout& lay) {
+  if (!pts) return TRIPS_ERR_INVALID_ARG;
+  if (pts->n != lay.P.n) return TRIPS_ERR_INVALID_ARG;
+  if (pts->n > 0 && (!pts->x || !pts->y || !pts->z || !pts->size_w || !pts->opacity || !pts->desc))
+    return TRIPS_ERR_INVALID_ARG;
+  if (pts->n > 0 && !aligned16(pts->desc)) return TRIPS_ERR_INVALID_ARG;
+  return TRIPS_OK;
+}
+
+template <int D>
+trips_status launch_forward(const Layout& lay, const trips_points& pts, float* pyr, char* sv,
+                            char* ws, hipStream_t st) {
+  const Params& P = lay.P;
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + lay.w_ctr);
+  uint32_t* H = reinterpret_cast<uint32_t*>(ws + lay.w_H);
+  uint32_t* tot = reinterpret_cast<uint32_t*>(ws + lay.w_tot);
+  uint32_t* pcnt = reinterpret_cast<uint32_t*>(ws + lay.w_pcnt);
+  uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + lay.w_pkey);
+  float* pgam = reinterpret_cast<float*>(ws + lay.w_pgam);
+  uint32_t* info = reinterpret_cast<uint32_t*>(sv + lay.s_info);
+  uint32_t* bin_start = reinterpret_cast<uint32_t*>(sv + lay.s_bin_start);
+  uint32_t* item_start = reinterpret_cast<uint32_t*>(sv + lay.s_item_start);
+  uint32_t* npix = reinterpret_cast<uint32_t*>(sv + lay.s_npix);
+  uint64_t* kkey = reinterpret_cast<uint64_t*>(sv + lay.s_kkey);
+  float* kgam = reinterpret_cast<float*>(sv + lay.s_kgam);
+  Entry* ent = reinterpret_cast<Entry*>(sv + lay.s_ent);
+  const size_t lds = size_t((lay.nbv_max + 1) / 2) * 4;
+
+  {
+    StageTimer tm(ST_FILL_F, st);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ctr, 64u, 0u);
+  }
+  TRIPS_HIP(hipGetLastError());
+  if (P.nblk > 0) {
+    StageTimer tm(ST_COUNT, st);
+    hipLaunchKernelGGL(k_count, dim3(P.nblk * P.V), dim3(256), lds, st, P, pts.x, pts.y, pts.z,
+                       pts.size_w, H);
+    TRIPS_HIP(hipGetLastError());
+  }
+  if (P.NB > 0) {
+    StageTimer tm(ST_COLSCAN, st);
+    if (P.nblk > 0) {
+      hipLaunchKernelGGL(k_colscan, dim3((P.NB + 63) / 64), dim3(256), 0, st, H, tot, P.NB, P.nblk);
+    } else {
+      hipLaunchKernelGGL(k_fill_u32, dim3((P.NB + 255) / 256), dim3(256), 0, st, tot, P.NB, 0u);
+    }
+    TRIPS_HIP(hipGetLastError());
+  }
+  {
+    StageTimer tm(ST_BINSCAN, st);
+    hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, tot, bin_start, item_start, info,
+                       P.NB, P.item_e);
+  }
+  TRIPS_HIP(hipGetLastError());
+  if (P.nblk > 0) {
+    StageTimer tm(ST_SCATTER, st);
+    hipLaunchKernelGGL(k_scatter, dim3(P.nblk * P.V), dim3(256), lds, st, P, pts.x, pts.y, pts.z,
+                       pts.size_w, pts.opacity, H, bin_start, ent, info);
+    TRIPS_HIP(hipGetLastError());
+  }
+  const int grid = int(std::min<uint64_t>(lay.icap, uint64_t(persistent_grid())));
+  {
+    StageTimer tm(ST_FWD_ITEMS, st);
+    hipLaunchKernelGGL(k_fwd_items<D>, dim3(grid), dim3(256), 0, st, P, bin_start, item_start,
+                       ent, pts.desc, ctr, pyr, npix, kkey, kgam, pcnt, pkey, pgam);
+  }
+  TRIPS_HIP(hipGetLastError());
+  const int mgrid = int(std::min<uint32_t>(P.NB, 2048u));
+  if (mgrid > 0) {
+    StageTimer tm(ST_FWD_MERGE, st);
+    hipLaunchKernelGGL(k_fwd_merge<D>, dim3(mgrid), dim3(256), 0, st, P, item_start, pcnt, pkey,
+                       pgam, pts.desc, pyr, npix, kkey, kgam);
+    TRIPS_HIP(hipGetLastError());
+  }
+  return TRIPS_OK;
+}
+
+template <int D>
+trips_status launch_backward(const Layout& lay, const trips_points& pts, const float* gpyr,
+                             const char* sv, char* ws, float* gx, float* gy, float* gz, float* gsw,
+                             float* ga, float* gd, hipStream_t st) {
+  const Params& P = lay.P;
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + lay.w_ctr);
+  float2* bst = reinterpret_cast<float2*>(ws + lay.w_bst);
+  float* rows = reinterpret_cast<float*>(ws + lay.w_rows);
+  const uint32_t* bin_start = reinterpret_cast<const uint32_t*>(sv + lay.s_bin_start);
+  const uint32_t* item_start = reinterpret_cast<const uint32_t*>(sv + lay.s_item_start);
+  const uint32_t* npix = reinterpret_cast<const uint32_t*>(sv + lay.s_npix);
+  const uint64_t* kkey = reinterpret_cast<const uint64_t*>(sv + lay.s_kkey);
+  const float* kgam = reinterpret_cast<const float*>(sv + lay.s_kgam);
+  const Entry* ent = reinterpret_cast<const Entry*>(sv + lay.s_ent);
+
+  {
+    StageTimer tm(ST_FILL_B, st);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ctr, 64u, 0u);
+  }
+  TRIPS_HIP(hipGetLastError());
+  if (P.NB > 0) {
+    StageTimer tm(ST_BWD_PIXELS, st);
+    hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, npix, kkey, kgam, pts.desc,
+                       gpyr, bst);
+    TRIPS_HIP(hipGetLastError());
+  }
+  const int grid = int(std::min<uint64_t>(lay.icap, uint64_t(persistent_grid() / 2)));
+  {
+    StageTimer tm(ST_BWD_ITEMS, st);
+    hipLaunchKernelGGL(k_bwd_items<D>, dim3(grid), dim3(256), 0, st, P, bin_start, item_start,
+                       ent, npix, kkey, bst, gpyr, ctr, rows);
+  }
+  TRIPS_HIP(hipGetLastError());
+  if (P.n > 0) {
+    StageTimer tm(ST_BWD_POINTS, st);
+    hipLaunchKernelGGL(k_bwd_points<D>, dim3(uint32_t((P.n + 255) / 256)), dim3(256), 0, st, P,
+                       pts.x, pts.y, pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd);
+    TRIPS_HIP(hipGetLastError());
+  }
+  return TRIPS_OK;
+}
+
+trips_status check_buffers(const Layout& lay, const void* saved, size_t saved_bytes,
+                           const void* ws, size_t ws_bytes, bool need_ws) {
+  if (!saved || !aligned(saved)) return TRIPS_ERR_INVALID_ARG;
+  if (saved_bytes < lay.saved_bytes) return TRIPS_ERR_WORKSPACE;
+  if (need_ws) {
+    if (!ws || !aligned(ws)) return TRIPS_ERR_INVALID_ARG;
+    if (ws_bytes < lay.ws_bytes) return TRIPS_ERR_WORKSPACE;
+  }
+  return TRIPS_OK;
+}
+
+}  // namespace
+
+struct trips_plan {
+  Layout lay;
+  trips_points pts;
+  float* pyr;
+  void* saved;
+  void* ws;
+  const float* gpyr;
+  float *gx, *gy, *gz, *gsw, *ga, *gd;
+  hipGraphExec_t exec[3];  // forward, backward, both
+};
+
+extern "C" {
+
+const char* trips_status_string(trips_status s) {
+  switch (s) {
+    case TRIPS_OK: return "ok";
+    case TRIPS_ERR_INVALID_ARG: return "invalid argument";
+    case TRIPS_ERR_WORKSPACE: return "workspace or saved buffer too small";
+    case TRIPS_ERR_CAPACITY: return "problem exceeds 32-bit fragment indexing";
+    case TRIPS_ERR_HIP: return "HIP error";
+    case TRIPS_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+int32_t trips_last_hip_error(void) { return g_last_hip; }
+
+trips_status trips_timing_enable(int32_t enable) {
+  g_timing.on = enable != 0;
+  g_timing.used = 0;
+  return TRIPS_OK;
+}
+
+trips_status trips_timing_read(float* ms, int32_t* calls) {
+  if (!ms || !calls) return TRIPS_ERR_INVALID_ARG;
+  for (int k = 0; k < NUM_STAGES; ++k) { ms[k] = 0.0f; calls[k] = 0; }
+  TimingState& t = g_timing;
+  for (size_t i = 0; i < t.used; ++i) {
+    TRIPS_HIP(hipEventSynchronize(t.pool[2 * i + 1]));
+    float e = 0.0f;
+    TRIPS_HIP(hipEventElapsedTime(&e, t.pool[2 * i], t.pool[2 * i + 1]));
+    ms[t.stage[i]] += e;
+    calls[t.stage[i]] += 1;
+  }
+  t.used = 0;
+  return TRIPS_OK;
+}
+
+const char* trips_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < NUM_STAGES) ? kStageNames[stage] : "";
+}
+
+trips_status trips_layer_layout(const trips_camera* cam, const trips_config* cfg, int32_t* dims,
+                                int64_t* offsets) {
+  if (!cam || !cfg) return TRIPS_ERR_INVALID_ARG;
+  if (cfg->num_layers < 1 || cfg->num_layers > MAXL) return TRIPS_ERR_INVALID_ARG;
+  if (cam->width < 1 || cam->height < 1 || cam->width > (1 << 16) || cam->height > (1 << 16))
+    return TRIPS_ERR_INVALID_ARG;
+  int64_t off = 0;
+  for (int L = 0; L < cfg->num_layers; ++L) {
+    const int64_t WL = (int64_t(cam->width) + (int64_t(1) << L) - 1) >> L;
+    const int64_t HL = (int64_t(cam->height) + (int64_t(1) << L) - 1) >> L;
+    if (dims) { dims[2 * L] = int32_t(WL); dims[2 * L + 1] = int32_t(HL); }
+    if (offsets) offsets[L] = off;
+    off += WL * HL;
+  }
+  if (offsets) offsets[cfg->num_layers] = off;
+  return TRIPS_OK;
+}
+
+trips_status trips_buffer_sizes(const trips_config* cfg, const trips_camera* cams, int32_t views,
+                                int64_t n, const trips_tuning* tun, size_t* ws_bytes,
+                                size_t* saved_bytes) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, n, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if (ws_bytes) *ws_bytes = lay.ws_bytes;
+  if (saved_bytes) *saved_bytes = lay.saved_bytes;
+  return TRIPS_OK;
+}
+
+trips_status trips_forward(const trips_config* cfg, const trips_points* pts,
+                           const trips_camera* cams, int32_t views, const trips_tuning* tun,
+                           float* pyr, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes,
+                           hipStream_t st) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if ((s = check_points(pts, lay)) != TRIPS_OK) return s;
+  if ((s = check_buffers(lay, saved, saved_bytes, ws, ws_bytes, true)) != TRIPS_OK) return s;
+  if (!pyr || !aligned16(pyr)) return TRIPS_ERR_INVALID_ARG;
+  char* sv = static_cast<char*>(saved);
+  char* w = static_cast<char*>(ws);
+  return cfg->desc_dim == 4 ? launch_forward<4>(lay, *pts, pyr, sv, w, st)
+                            : launch_forward<8>(lay, *pts, pyr, sv, w, st);
+}
+
+trips_status trips_backward(const trips_config* cfg, const trips_points* pts,
+                            const trips_camera* cams, int32_t views, const trips_tuning* tun,
+                            const float* gpyr, const void* saved, size_t saved_bytes, void* ws,
+                            size_t ws_bytes, float* gx, float* gy, float* gz, float* gsw,
+                            float* ga, float* gd, hipStream_t st) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if ((s = check_points(pts, lay)) != TRIPS_OK) return s;
+  if ((s = check_buffers(lay, saved, saved_bytes, ws, ws_bytes, true)) != TRIPS_OK) return s;
+  if (!gpyr || !aligned16(gpyr)) return TRIPS_ERR_INVALID_ARG;
+  if (lay.P.n > 0 && (!gx || !gy || !gz || !gsw || !ga || !gd || !aligned16(gd)))
+    return TRIPS_ERR_INVALID_ARG;
+  const char* sv = static_cast<const char*>(saved);
+  char* w = static_cast<char*>(ws);
+  return cfg->desc_dim == 4 ? launch_backward<4>(lay, *pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st)
+                            : launch_backward<8>(lay, *pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st);
+}
+
+trips_status trips_export_fragments(const trips_config* cfg, const trips_camera* cams,
+                                    int32_t views, const trips_tuning* tun, const void* saved,
+                                    size_t saved_bytes, int32_t* counts, int32_t* ids,
+                                    hipStream_t st) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, 0, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if (!saved || !aligned(saved) || !counts || !ids) return TRIPS_ERR_INVALID_ARG;
+  // the texel tables do not depend on n; only their part of `saved` is read
+  if (saved_bytes < lay.s_ent) return TRIPS_ERR_WORKSPACE;
+  const char* sv = static_cast<const char*>(saved);
+  if (lay.P.NB > 0) {
+    StageTimer tm(ST_EXPORT, st);
+    hipLaunchKernelGGL(k_export, dim3(lay.P.NB), dim3(256), 0, st, lay.P,
+                       reinterpret_cast<const uint32_t*>(sv + lay.s_npix),
+                       reinterpret_cast<const uint64_t*>(sv + lay.s_kkey), counts, ids);
+    TRIPS_HIP(hipGetLastError());
+  }
+  return TRIPS_OK;
+}
+
+trips_status trips_forward_stats(const trips_config* cfg, const trips_camera* cams, int32_t views,
+                                 const trips_tuning* tun, const void* saved, size_t saved_bytes,
+                                 int64_t* stats, hipStream_t st) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, 0, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if (!saved || !aligned(saved) || !stats) return TRIPS_ERR_INVALID_ARG;
+  if (saved_bytes < lay.s_bin_start) return TRIPS_ERR_WORKSPACE;
+  uint32_t info[3] = {0, 0, 0};
+  TRIPS_HIP(hipMemcpyAsync(info, static_cast<const char*>(saved) + lay.s_info, sizeof(info),
+                           hipMemcpyDeviceToHost, st));
+  TRIPS_HIP(hipStreamSynchronize(st));
+  stats[0] = info[0];
+  stats[1] = info[1];
+  stats[2] = lay.P.NB;
+  stats[3] = info[2];
+  return TRIPS_OK;
+}
+
+trips_status trips_plan_create(const trips_config* cfg, const trips_points* pts,
+                               const trips_camera* cams, int32_t views, const trips_tuning* tun,
+                               float* pyr, void* saved, size_t saved_bytes, void* ws,
+                               size_t ws_bytes, const float* gpyr, float* gx, float* gy, float* gz,
+                               float* gsw, float* ga, float* gd, hipStream_t st,
+                               trips_plan** out) {
+  if (!out || !st) return TRIPS_ERR_INVALID_ARG;  // the null stream cannot be captured
+  *out = nullptr;
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if ((s = check_points(pts, lay)) != TRIPS_OK) return s;
+  if ((s = check_buffers(lay, saved, saved_bytes, ws, ws_bytes, true)) != TRIPS_OK) return s;
+  if (!pyr || !aligned16(pyr)) return TRIPS_ERR_INVALID_ARG;
+  const bool bwd = gpyr != nullptr;
+  if (bwd && (!aligned16(gpyr) ||
+              (lay.P.n > 0 && (!gx || !gy || !gz || !gsw || !ga || !gd || !aligned16(gd)))))
+    return TRIPS_ERR_INVALID_ARG;
+  trips_plan* pl = new (std::nothrow) trips_plan();
+  if (!pl) return TRIPS_ERR_INVALID_ARG;
+  pl->lay = lay;
+  pl->pts = *pts;
+  pl->pyr = pyr; pl->saved = saved; pl->ws = ws; pl->gpyr = gpyr;
+  pl->gx = gx; pl->gy = gy; pl->gz = gz; pl->gsw = gsw; pl->ga = ga; pl->gd = gd;
+  for (int which = 1; which <= 3; ++which) {
+    pl->exec[which - 1] = nullptr;
+    if ((which & 2) && !bwd) continue;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { g_last_hip = e; trips_plan_destroy(pl); return TRIPS_ERR_HIP; }
+    trips_status ls = TRIPS_OK;
+    char* sv = static_cast<char*>(saved);
+    char* w = static_cast<char*>(ws);
+    if (which & 1)
+      ls = lay.P.D == 4 ? launch_forward<4>(lay, pl->pts, pyr, sv, w, st)
+                        : launch_forward<8>(lay, pl->pts, pyr, sv, w, st);
+    if (ls == TRIPS_OK && (which & 2))
+      ls = lay.P.D == 4 ? launch_backward<4>(lay, pl->pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st)
+                        : launch_backward<8>(lay, pl->pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st);
+    e = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(st, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+      }
+    }
+    if (ls != TRIPS_OK || e != hipSuccess) {
+      if (e != hipSuccess) g_last_hip = e;
+      if (g) (void)hipGraphDestroy(g);
+      trips_plan_destroy(pl);
+      return ls != TRIPS_OK ? ls : TRIPS_ERR_HIP;
+    }
+    e = hipGraphInstantiate(&pl->exec[which - 1], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { g_last_hip = e; pl->exec[which - 1] = nullptr; trips_plan_destroy(pl); return TRIPS_ERR_HIP; }
+  }
+  *out = pl;
+  return TRIPS_OK;
+}
+
+trips_status trips_plan_launch(trips_plan* pl, int32_t which, hipStream_t st) {
+  if (!pl || which < 1 || which > 3 || !pl->exec[which - 1]) return TRIPS_ERR_INVALID_ARG;
+  TRIPS_HIP(hipGraphLaunch(pl->exec[which - 1], st));
+  return TRIPS_OK;
+}
+
+void trips_plan_destroy(trips_plan* pl) {
+  if (!pl) return;
+  for (auto& e : pl->exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  delete pl;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and
+validates arguments before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trips.h")
+
+
+def _lib():
+    import paper_2401_06003_amd as tp
+    if not os.path.exists(tp.LIB_PATH):
+        pytest.skip("libtrips.so not built")
+    return tp, tp.lib()
+
+
+def test_exports_every_declared_symbol():
+    tp, L = _lib()
+    names = set(re.findall(r"\b(trips_[a-z_]+)\s*\(", open(HEADER).read()))
+    assert len(names) >= 11
+    for name in sorted(names):
+        assert hasattr(L, name), name
+
+
+def _cam(W=1920, H=1080):
+    import scenes
+    return scenes.camera([[1, 0, 0], [0, 1, 0], [0, 0, 1]], (0, 0, 3), W, H)
+
+
+def test_layer_layout_and_sizes():
+    tp, L = _lib()
+    dims, offs = tp.layer_layout(_cam(), 8)
+    assert dims[0] == (1920, 1080) and dims[7] == (15, 9)
+    assert offs[-1] == 2764845
+    cams = (tp.Camera * 1)(tp.make_camera(_cam()))
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    st = L.trips_buffer_sizes(ctypes.byref(tp.make_config(8, 4)), cams, 1, 2_000_000, None,
+                              ctypes.byref(ws), ctypes.byref(sv))
+    assert st == 0 and ws.value > 0 and sv.value > 0
+    assert sv.value % 256 == 0 and ws.value % 256 == 0
+
+
+@pytest.mark.parametrize("cfg,views,n,tune,code", [
+    ((0, 16, 0.25, 4), 1, 10, None, -1),     # no layers
+    ((13, 16, 0.25, 4), 1, 10, None, -1),    # too many layers
+    ((5, 8, 0.25, 4), 1, 10, None, -5),      # list clamp other than 16
+    ((5, 16, 0.25, 6), 1, 10, None, -5),     # descriptor width not built
+    ((5, 16, 1.5, 4), 1, 10, None, -1),      # eps out of range
+    ((5, 16, 0.25, 4), 0, 10, None, -1),     # no views
+    ((5, 16, 0.25, 4), 17, 10, None, -1),    # too many views
+    ((5, 16, 0.25, 4), 1, -1, None, -1),     # negative point count
+    ((5, 16, 0.25, 4), 1, 10, (12, 0, 0), -1),   # tile width not a power of two
+    ((5, 16, 0.25, 4), 1, 10, (16, 100, 0), -1),  # points per block too small
+])
+def test_invalid_arguments(cfg, views, n, tune, code):
+    tp, L = _lib()
+    cams = (tp.Camera * 17)(*[tp.make_camera(_cam(64, 48)) for _ in range(17)])
+    t = tp.make_tuning(*tune) if tune else None
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    st = L.trips_buffer_sizes(ctypes.byref(tp.make_config(*cfg[:1], cfg[3], cfg[2], cfg[1])),
+                              cams, views, n, ctypes.byref(t) if t else None, ctypes.byref(ws),
+                              ctypes.byref(sv))
+    assert st == code
+
+
+def test_bad_camera_rejected():
+    tp, L = _lib()
+    c = _cam(64, 48)
+    c["znear"] = 0.0
+    cams = (tp.Camera * 1)(tp.make_camera(c))
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.trips_buffer_sizes(ctypes.byref(tp.make_config(5, 4)), cams, 1, 10, None,
+                                ctypes.byref(ws), ctypes.byref(sv)) == -1
+
+
+def test_forward_validates_before_launch():
+    """Every failing check returns before any launch, so these run without a GPU."""
+    tp, L = _lib()
+    cfg = tp.make_config(5, 4)
+    cams = (tp.Camera * 1)(tp.make_camera(_cam(64, 48)))
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.trips_buffer_sizes(ctypes.byref(cfg), cams, 1, 100, None, ctypes.byref(ws),
+                                ctypes.byref(sv)) == 0
+    fake = 1 << 20  # aligned, never dereferenced: every call below fails validation first
+    pts = tp.Points(fake, fake, fake, fake, fake, fake, 100)
+    null_pts = tp.Points(0, 0, 0, 0, 0, 0, 100)
+    f = L.trips_forward
+    # null point arrays
+    assert f(ctypes.byref(cfg), ctypes.byref(null_pts), cams, 1, None, fake, fake, sv.value, fake,
+             ws.value, None) == -1
+    # saved / workspace too small
+    assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake, sv.value - 256, fake,
+             ws.value, None) == -2
+    assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake, sv.value, fake,
+             ws.value - 256, None) == -2
+    # misaligned saved buffer
+    assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake + 8, sv.value, fake,
+             ws.value, None) == -1
+    # point count differs from the one the buffers were sized for is still validated per call
+    b = L.trips_backward
+    assert b(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, 0, fake, sv.value, fake, ws.value,
+             fake, fake, fake, fake, fake, fake, None) == -1   # null grad_pyramid
+    assert L.trips_status_string(-3) == b"problem exceeds 32-bit fragment indexing"
