@@ -33,8 +33,36 @@ def build(force=False):
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        override = os.environ.get("TRIPS_ORACLE_LIB")
+        if override:  # a test build of the oracle (see tests/test_oracle_mutations.py)
+            _lib = _configure(ctypes.CDLL(override))
+        else:
+            build()
+            _lib = _configure(ctypes.CDLL(_LIB))
+    return _lib
+
+
+class use_library:
+    """Context manager: route every call of this module to another build of the oracle
+    (used by the tests that plant mistakes in a copy of the source)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _configure(ctypes.CDLL(self.path))
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _configure(L):
+    if True:
         dp = ctypes.POINTER(ctypes.c_double)
         i32p = ctypes.POINTER(ctypes.c_int32)
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -54,8 +82,7 @@ def lib():
         L.oracle_backward.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int, c_int,
                                       c_int, c_double, c_int, u8p, dp, dp, dp, dp, dp, dp, dp]
         L.oracle_backward.restype = c_int
-        _lib = L
-    return _lib
+    return L
 
 
 def _d(a):

@@ -35,7 +35,7 @@
  *
  * Readings of the paper that this file fixes (the paper is silent or garbled):
  *   - log is log2 (the layer texel size is 2^L); computed exactly with ilogb.
- *   - "s_i = 0 and s < 1" means layer index 0.
+ *   - the second case of Eq. 5 (points smaller than a pixel) writes to layer index 0.
  *   - s an exact power of two 2^e: one layer e with iota = 1 (the Eq. 5
  *     denominator would be 0).  s >= 2^(n-1): the coarsest layer only, iota = 1.
  *   - texel (i, j) of layer L has its centre at ((i + 0.5) 2^L, (j + 0.5) 2^L)

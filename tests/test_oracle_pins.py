@@ -132,6 +132,9 @@ def test_projection_pinhole():
         R = (q * np.sign(np.diag(r))).astype(np.float32)
         t = rng.uniform(-1, 1, 3).astype(np.float32) + np.float32([0, 0, 4])
         c = scenes.camera(R, t, 1920, 1080)
+        # non-square pixels and an off-centre principal point
+        c["fy"] = np.float32(float(c["fx"]) * 0.8)
+        c["cy"] = np.float32(float(c["cy"]) + 13.25)
         X = rng.uniform(-1, 1, (500, 3)).astype(np.float32)
         sw = rng.uniform(0.001, 0.05, 500).astype(np.float32)
         pts = {"x": X[:, 0].copy(), "y": X[:, 1].copy(), "z": X[:, 2].copy(), "sw": sw}
@@ -167,6 +170,18 @@ def test_gather_equals_scatter(seed, ties):
     assert np.array_equal(a[2], b[2]), "kept ids or their order differ"
     assert np.array_equal(a[0], b[0]), "blended values differ"
     assert a[1].sum() > 100
+
+
+def test_gather_equals_scatter_non_square_pixels():
+    sc = scenes.random_small(5, n=48, W=24, H=20, nlayers=4)
+    pts, c = sc["points"], dict(sc["cams"][0])
+    c["fy"] = np.float32(float(c["fx"]) * 0.7)
+    c["cy"] = np.float32(8.5)
+    a = oracle.forward(pts, c, 4)
+    b = gather.render(pts, c, 4)
+    assert a[1].sum() > 50
+    for k in range(3):
+        assert np.array_equal(a[k], b[k])
 
 
 def test_gather_equals_scatter_clamped_lists():
