@@ -76,11 +76,11 @@ typedef struct {
   int64_t n;
 } trips_points;
 
-/* Launch-shape choices (all optional: pass NULL for the defaults).  tile_w is the
-   width in texels of a screen tile (16x16 by default; tiles always hold 256 texels:
-   8x32, 16x16, 32x8, 64x4).  points_per_block is the number of points one binning
-   workgroup histograms (256..65535).  item_entries is the number of tile entries one
-   sort/blend workgroup consumes before handing over to a merge (256..65536). */
+/* Launch-shape choices (all optional: pass NULL, or 0 in a field, for the defaults).
+   tile_w is the width in texels of a screen tile (16x16 by default; tiles always hold
+   256 texels: 8x32, 16x16, 32x8, 64x4).  points_per_block is the number of points one
+   binning workgroup histograms (256..65535).  item_entries is the number of tile entries
+   one sort/blend workgroup consumes before handing over to a merge (256..65536). */
 typedef struct {
   int32_t tile_w;
   int32_t points_per_block;
@@ -151,11 +151,26 @@ int32_t trips_last_hip_error(void);
    milliseconds and the number of launches since the last read (or enable), then resets.
    Stage k is named by trips_stage_name(k), k < TRIPS_NUM_STAGES.  The events are host
    objects owned by the library; no device memory is allocated. */
-#define TRIPS_NUM_STAGES 12
+#define TRIPS_NUM_STAGES 11
 trips_status trips_timing_enable(int32_t enable);
 trips_status trips_timing_read(float* ms_host /*[TRIPS_NUM_STAGES]*/,
                                int32_t* launches_host /*[TRIPS_NUM_STAGES]*/);
 const char* trips_stage_name(int32_t stage);
+
+/* Autotuner.  Times forward + backward for each of the ncand launch shapes (one warm-up,
+   then `reps` timed repetitions, HIP events on `stream`, which is synchronised) and
+   returns the fastest in *best and every mean time in ms_host[ncand] (milliseconds).
+   All candidates are validated first; the buffers must be large enough for every one of
+   them (trips_buffer_sizes per candidate, take the maximum).  The outputs hold the result
+   of the last candidate timed. */
+trips_status trips_autotune(const trips_config* cfg_host, const trips_points* pts_host,
+                            const trips_camera* cams_host, int32_t views,
+                            const trips_tuning* candidates_host, int32_t ncand, int32_t reps,
+                            float* pyramid_out, void* saved, size_t saved_bytes, void* workspace,
+                            size_t workspace_bytes, const float* grad_pyramid, float* grad_x,
+                            float* grad_y, float* grad_z, float* grad_size_w,
+                            float* grad_opacity, float* grad_desc, trips_tuning* best_host,
+                            float* ms_host, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------
    Plan: the batched multi-view form captured once in a HIP graph and replayed.

@@ -79,6 +79,10 @@ def lib():
         L.trips_timing_read.restype = c_int32
         L.trips_stage_name.argtypes = [c_int32]
         L.trips_stage_name.restype = ctypes.c_char_p
+        L.trips_autotune.argtypes = ([P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_int32,
+                                      c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_size_t]
+                                     + [c_void_p] * 7 + [P(Tuning), P(c_float), c_void_p])
+        L.trips_autotune.restype = c_int32
         L.trips_plan_create.argtypes = ([P(Config), P(Points), P(Camera), c_int32, P(Tuning),
                                          c_void_p, c_void_p, c_size_t, c_void_p, c_size_t]
                                         + [c_void_p] * 8 + [P(c_void_p)])
@@ -95,6 +99,8 @@ def lib():
 
 def _check(status, what):
     if status != 0:
+        if status == -4:
+            what = "%s (hip error %d)" % (what, lib().trips_last_hip_error())
         raise TripsError(status, what)
 
 
@@ -251,7 +257,7 @@ class Renderer:
         return out
 
 
-NUM_STAGES = 12
+NUM_STAGES = 11
 
 
 def timing_enable(on=True):
@@ -298,6 +304,69 @@ class Plan:
         if getattr(self, "h", None) and _lib is not None:
             _lib.trips_plan_destroy(self.h)
             self.h = None
+
+
+# Launch shapes tried by default: tile width x points per binning block x entries per item.
+DEFAULT_CANDIDATES = [(tw, pb, ie) for tw in (8, 16, 32) for pb in (4096, 8192)
+                      for ie in (2048, 4096, 8192)]
+
+
+def autotune(cams, num_layers, desc_dim, x, y, z, sw, alpha, desc, candidates=None, reps=3,
+             cache_path=None, device="cuda"):
+    """Pick the fastest launch shape for this workload with the library's autotuner
+    (trips_autotune: forward + backward timed with HIP events per candidate).
+
+    Results are cached in a JSON file (cache_path, default $TRIPS_TUNE_CACHE if set) keyed
+    by the device name and the workload's shape.  Returns (Tuning, {candidate: ms})."""
+    import json
+    if isinstance(cams, dict):
+        cams = [cams]
+    dev = torch.device(device)
+    n = int(x.numel())
+    cand = [tuple(int(v) for v in c) for c in (candidates or DEFAULT_CANDIDATES)]
+    key = json.dumps({"device": torch.cuda.get_device_name(dev), "n": n, "layers": int(num_layers),
+                      "D": int(desc_dim), "views": [(int(c["W"]), int(c["H"])) for c in cams],
+                      "candidates": cand})
+    cache_path = cache_path or os.environ.get("TRIPS_TUNE_CACHE")
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return make_tuning(*cache[key]["best"]), {tuple(k): v for k, v in cache[key]["ms"]}
+    cam_arr = (Camera * len(cams))(*[make_camera(c) for c in cams])
+    cfg = make_config(num_layers, desc_dim)
+    tunes = (Tuning * len(cand))(*[make_tuning(*c) for c in cand])
+    ws_max = sv_max = 0
+    for k in range(len(cand)):
+        ws, sv = c_size_t(), c_size_t()
+        _check(lib().trips_buffer_sizes(ctypes.byref(cfg), cam_arr, len(cams), n,
+                                        ctypes.byref(tunes[k]), ctypes.byref(ws), ctypes.byref(sv)),
+               "trips_buffer_sizes")
+        ws_max, sv_max = max(ws_max, ws.value), max(sv_max, sv.value)
+    workspace = _aligned_bytes(ws_max, dev)
+    saved = _aligned_bytes(sv_max, dev)
+    texels = sum(layer_layout(c, num_layers)[1][-1] for c in cams)
+    pyr = torch.empty(texels * desc_dim, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    gpyr = torch.randn(texels * desc_dim, dtype=torch.float32, device=dev, generator=gen)
+    grads = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(5)]
+    grads.append(torch.empty((n, desc_dim), dtype=torch.float32, device=dev))
+    pts = Points(x.data_ptr(), y.data_ptr(), z.data_ptr(), sw.data_ptr(), alpha.data_ptr(),
+                 desc.data_ptr(), n)
+    best = Tuning()
+    ms = (c_float * len(cand))()
+    _check(lib().trips_autotune(ctypes.byref(cfg), ctypes.byref(pts), cam_arr, len(cams), tunes,
+                                len(cand), int(reps), _ptr(pyr), _ptr(saved), sv_max,
+                                _ptr(workspace), ws_max, _ptr(gpyr), *[_ptr(g) for g in grads],
+                                ctypes.byref(best), ms, _stream()), "trips_autotune")
+    result = {cand[k]: ms[k] for k in range(len(cand))}
+    if cache_path:
+        cache[key] = {"best": [best.tile_w, best.points_per_block, best.item_entries],
+                      "ms": [[list(k), v] for k, v in result.items()]}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best, result
 
 
 class TripsSplat(torch.autograd.Function):

@@ -243,6 +243,13 @@ __device__ __forceinline__ void top_insert(uint64_t (&k)[KEEP], float (&g)[KEEP]
 }
 
 // ------------------------------------------------------------------------------------
+// LDS counters packed two per word (16 bits each): add one to counter c, return its old value.
+__device__ __forceinline__ uint32_t add16(uint32_t* words, uint32_t c) {
+  const uint32_t sh = (c & 1u) * 16u;
+  return (atomicAdd(&words[c >> 1], 1u << sh) >> sh) & 0xffffu;
+}
+
+// ------------------------------------------------------------------------------------
 // Kernels.
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t value) {
@@ -277,13 +284,15 @@ __device__ __forceinline__ void for_each_entry(const Params& P, const ViewP& c, 
   }
 }
 
+constexpr int BIN_THREADS = 1024;  // threads of a count / scatter workgroup
+
 // count: LDS histogram (two 16-bit counters per word) of the entries of one point block
 // in one view; writes row `blk` of H for the bins of that view.
-__global__ __launch_bounds__(256) void k_count(const Params P, const float* __restrict__ X,
-                                               const float* __restrict__ Y,
-                                               const float* __restrict__ Z,
-                                               const float* __restrict__ SW,
-                                               uint32_t* __restrict__ H) {
+__global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const float* __restrict__ X,
+                                                       const float* __restrict__ Y,
+                                                       const float* __restrict__ Z,
+                                                       const float* __restrict__ SW,
+                                                       uint32_t* __restrict__ H) {
   extern __shared__ uint32_t hist[];
   const int v = blockIdx.x % P.V;
   const uint32_t blk = blockIdx.x / P.V;
@@ -296,8 +305,7 @@ __global__ __launch_bounds__(256) void k_count(const Params P, const float* __re
   for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     for_each_entry(P, c, X[p], Y[p], Z[p], SW[p],
                    [&](uint32_t bin, uint32_t, int, const Foot&, const Geo&) {
-                     uint32_t lb = bin - c.bin_base;
-                     atomicAdd(&hist[lb >> 1], 1u << ((lb & 1u) * 16u));
+                     add16(hist, bin - c.bin_base);
                    });
   }
   __syncthreads();
@@ -307,13 +315,15 @@ __global__ __launch_bounds__(256) void k_count(const Params P, const float* __re
 }
 
 // colscan: per bin, exclusive prefix of H over point blocks (in place) and the bin total.
-// Workgroup = 64 bins x 4 block segments.
-__global__ __launch_bounds__(256) void k_colscan(uint32_t* __restrict__ H, uint32_t* __restrict__ tot,
-                                                 uint32_t NB, uint32_t nblk) {
-  __shared__ uint32_t ssum[4][64];
+// Workgroup = 64 bins x 16 block segments.
+constexpr int CS_SEG = 16;
+__global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ H,
+                                                         uint32_t* __restrict__ tot, uint32_t NB,
+                                                         uint32_t nblk) {
+  __shared__ uint32_t ssum[CS_SEG][64];
   const uint32_t lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
   const uint32_t b = blockIdx.x * 64 + lane;
-  const uint32_t per = (nblk + 3) / 4;
+  const uint32_t per = (nblk + CS_SEG - 1) / CS_SEG;
   const uint32_t k0 = min(nblk, seg * per), k1 = min(nblk, k0 + per);
   uint32_t sum = 0;
   if (b < NB)
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(256) void k_colscan(uint32_t* __restrict__ H, uint3
   uint32_t run = 0;
   for (uint32_t s = 0; s < seg; ++s) run += ssum[s][lane];
   if (b < NB) {
-    if (seg == 3) tot[b] = run + sum;
+    if (seg == CS_SEG - 1) tot[b] = run + sum;
     for (uint32_t k = k0; k < k1; ++k) {
       size_t o = size_t(k) * NB + b;
       uint32_t h = H[o];
@@ -335,15 +345,17 @@ __global__ __launch_bounds__(256) void k_colscan(uint32_t* __restrict__ H, uint3
 
 // binscan (one workgroup of 1024): bin_start = exclusive scan of totals; every bin is cut
 // into max(1, ceil(total / item_e)) work items; item_start = exclusive scan of those.
+// Bins with more than one item are listed in multi_bins (their partial lists are merged).
 __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ tot,
                                                   uint32_t* __restrict__ bin_start,
                                                   uint32_t* __restrict__ item_start,
+                                                  uint32_t* __restrict__ multi_bins,
                                                   uint32_t* __restrict__ info, uint32_t NB,
                                                   uint32_t item_e) {
   __shared__ uint32_t ws[16];
-  uint32_t carry_e = 0, carry_i = 0;
+  uint32_t carry_e = 0, carry_i = 0, carry_m = 0;
   for (uint32_t base = 0; base < NB; base += 4096) {
-    uint32_t e[4], it[4], se = 0, si = 0;
+    uint32_t e[4], it[4], se = 0, si = 0, sm = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       uint32_t idx = base + threadIdx.x * 4 + k;
@@ -351,22 +363,27 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
       it[k] = idx < NB ? max(1u, (e[k] + item_e - 1) / item_e) : 0u;
       se += e[k];
       si += it[k];
+      sm += it[k] > 1 ? 1u : 0u;
     }
-    uint32_t te, ti;
+    uint32_t te, ti, tm;
     uint32_t oe = block_excl_scan<16>(se, ws, te);
     uint32_t oi = block_excl_scan<16>(si, ws, ti);
+    uint32_t om = block_excl_scan<16>(sm, ws, tm);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       uint32_t idx = base + threadIdx.x * 4 + k;
       if (idx < NB) {
         bin_start[idx] = carry_e + oe;
         item_start[idx] = carry_i + oi;
+        if (it[k] > 1) multi_bins[carry_m + om] = idx;
       }
       oe += e[k];
       oi += it[k];
+      om += it[k] > 1 ? 1u : 0u;
     }
     carry_e += te;
     carry_i += ti;
+    carry_m += tm;
   }
   if (threadIdx.x == 0) {
     bin_start[NB] = carry_e;
@@ -374,29 +391,38 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
     info[0] = carry_e;
     info[1] = carry_i;
     info[2] = 0;  // visible (point, view) pairs, accumulated by the scatter pass
+    info[3] = carry_m;
   }
 }
 
 // scatter: the count pass again, with LDS ranks; entry -> bin_start + H (column prefix) + rank.
-__global__ __launch_bounds__(256) void k_scatter(const Params P, const float* __restrict__ X,
-                                                 const float* __restrict__ Y,
-                                                 const float* __restrict__ Z,
-                                                 const float* __restrict__ SW,
-                                                 const float* __restrict__ A,
-                                                 const uint32_t* __restrict__ H,
-                                                 const uint32_t* __restrict__ bin_start,
-                                                 Entry* __restrict__ ent,
-                                                 uint32_t* __restrict__ info) {
-  extern __shared__ uint32_t hist[];
+// With STAGED, the block's first position in every bin of its view is staged in LDS first;
+// otherwise it is read per entry (views whose tables exceed 64 KB of LDS).
+template <bool STAGED>
+__global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const float* __restrict__ X,
+                                                         const float* __restrict__ Y,
+                                                         const float* __restrict__ Z,
+                                                         const float* __restrict__ SW,
+                                                         const float* __restrict__ A,
+                                                         const uint32_t* __restrict__ H,
+                                                         const uint32_t* __restrict__ bin_start,
+                                                         Entry* __restrict__ ent,
+                                                         uint32_t* __restrict__ info) {
+  extern __shared__ uint32_t lds[];
   __shared__ uint32_t s_vis;
-  if (threadIdx.x == 0) s_vis = 0;
   const int v = blockIdx.x % P.V;
   const uint32_t blk = blockIdx.x / P.V;
   const ViewP& c = P.view[v];
   const uint32_t nw = (c.nbins + 1) >> 1;
+  uint32_t* hist = lds;            // packed 16-bit ranks
+  uint32_t* base = lds + nw;       // first slot of this block in each bin
+  const uint32_t* row = H + size_t(blk) * P.NB + c.bin_base;
+  const uint32_t* bs = bin_start + c.bin_base;
+  if (threadIdx.x == 0) s_vis = 0;
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) hist[i] = 0;
+  if (STAGED)
+    for (uint32_t i = threadIdx.x; i < c.nbins; i += blockDim.x) base[i] = bs[i] + row[i];
   __syncthreads();
-  const uint32_t* row = H + size_t(blk) * P.NB;
   const int64_t p0 = int64_t(blk) * P.pb;
   const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
   uint32_t vis = 0;
@@ -406,11 +432,8 @@ __global__ __launch_bounds__(256) void k_scatter(const Params P, const float* __
     for_each_entry(P, c, X[p], Y[p], Z[p], SW[p],
                    [&](uint32_t bin, uint32_t slot, int sel, const Foot& ft, const Geo& g) {
                      any = true;
-                     uint32_t lb = bin - c.bin_base;
-                     uint32_t sh = (lb & 1u) * 16u;
-                     uint32_t old = atomicAdd(&hist[lb >> 1], 1u << sh);
-                     uint32_t rank = (old >> sh) & 0xffffu;
-                     uint32_t dst = bin_start[bin] + row[bin] + rank;
+                     const uint32_t lb = bin - c.bin_base;
+                     const uint32_t rank = add16(hist, lb);
                      Entry e;
                      e.idx = uint32_t(p);
                      e.zbits = __float_as_uint(g.zc);
@@ -418,7 +441,7 @@ __global__ __launch_bounds__(256) void k_scatter(const Params P, const float* __
                      e.v = ft.v;
                      e.ia = g.io[sel] * alpha;
                      e.slot = slot;
-                     ent[dst] = e;
+                     ent[(STAGED ? base[lb] : bs[lb] + row[lb]) + rank] = e;
                    });
     vis += any ? 1u : 0u;
   }
@@ -456,25 +479,14 @@ __device__ __forceinline__ uint32_t entry_corners(const Entry& e, const BinInfo&
   return mask;
 }
 
-__device__ __forceinline__ uint32_t find_item_bin(const uint32_t* __restrict__ item_start,
-                                                  uint32_t NB, uint32_t it) {
-  // largest b with item_start[b] <= it (item_start is non-decreasing, every bin >= 1 item)
-  uint32_t lo = 0, hi = NB;  // invariant: item_start[lo] <= it < item_start[hi]
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (item_start[mid] <= it) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 // Blend the kept fragments of one texel front to back (Eq. 6-7) and write its outputs.
 template <int D>
 __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& bi, uint32_t b,
                                                const uint64_t (&kk)[KEEP], const float (&kg)[KEEP],
                                                uint32_t n, const float* __restrict__ desc,
                                                float* __restrict__ pyr, uint32_t* __restrict__ npix,
-                                               uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
-  const int t = threadIdx.x;
+                                               uint64_t* __restrict__ kkey, float* __restrict__ kgam,
+                                               int t) {
   const int lth = 8 - P.ltw;
   const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
   const int j = (bi.ty << lth) + (t >> P.ltw);
@@ -483,21 +495,33 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
 #pragma unroll
   for (int d = 0; d < D; ++d) C[d] = 0.0f;
   float T = 1.0f;
+  // descriptor gathers are issued in batches of GB before they are used
+  constexpr int GB = D > 4 ? 4 : 8;
 #pragma unroll
-  for (int m = 0; m < KEEP; ++m) {
-    if (uint32_t(m) < k) {
-      const uint32_t idx = uint32_t(kk[m]);
-      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx) * D);
-      const float w = T * kg[m];
+  for (int m0 = 0; m0 < KEEP; m0 += GB) {
+    float4 tv[GB][D / 4];
 #pragma unroll
-      for (int q = 0; q < D / 4; ++q) {
-        float4 tv = tp[q];
-        C[4 * q + 0] += w * tv.x;
-        C[4 * q + 1] += w * tv.y;
-        C[4 * q + 2] += w * tv.z;
-        C[4 * q + 3] += w * tv.w;
+    for (int q = 0; q < GB; ++q) {
+      const int m = m0 + q;
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(uint32_t(kk[m])) * D);
+#pragma unroll
+      for (int r = 0; r < D / 4; ++r)
+        tv[q][r] = uint32_t(m) < k ? tp[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const int m = m0 + q;
+      if (uint32_t(m) < k) {
+        const float w = T * kg[m];
+#pragma unroll
+        for (int r = 0; r < D / 4; ++r) {
+          C[4 * r + 0] += w * tv[q][r].x;
+          C[4 * r + 1] += w * tv[q][r].y;
+          C[4 * r + 2] += w * tv[q][r].z;
+          C[4 * r + 3] += w * tv[q][r].w;
+        }
+        T = T * (1.0f - kg[m]);
       }
-      T = T * (1.0f - kg[m]);
     }
   }
   if (i < bi.WL && j < bi.HL) {
@@ -515,119 +539,233 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
     }
 }
 
-constexpr int SUB_E = 256;            // entries per LDS round (one per thread)
+constexpr int EPT = 2;                // entries per thread per LDS round
+constexpr int SUB_E = EPT * TP;       // entries per LDS round
 constexpr int SUB_F = 4 * SUB_E;      // fragments per LDS round (at most 4 per entry)
 
-// fwd_items: persistent; one workgroup per work item, coarse layers first.
+// item_bins: the work table in processing order (coarse layers, which hold the long lists,
+// come last in bin order and are processed first): slot w = total - 1 - it describes item it
+// as {bin, first entry, end entry, it | (bin has several items) << 31}.
+__global__ __launch_bounds__(256) void k_item_bins(const uint32_t* __restrict__ item_start,
+                                                   const uint32_t* __restrict__ bin_start,
+                                                   uint4* __restrict__ work, uint32_t NB,
+                                                   uint32_t item_e) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const uint32_t total = item_start[NB];
+  const uint32_t i0 = item_start[b], i1 = item_start[b + 1];
+  const uint32_t e_end = bin_start[b + 1];
+  const uint32_t multi = (i1 - i0 > 1) ? 0x80000000u : 0u;
+  for (uint32_t it = i0; it < i1; ++it) {
+    const uint32_t e0 = bin_start[b] + (it - i0) * item_e;
+    work[total - 1 - it] = make_uint4(b, e0, min(e0 + item_e, e_end), it | multi);
+  }
+}
+
+// fwd_items: one workgroup per work item (coarse layers first).  Each LDS round expands
+// SUB_E entries into fragments, counting-sorts them by texel and lets the thread owning the
+// texel insert them into its register top-16.  A fragment whose key is not below the
+// texel's current 16th key is only counted, never sorted.
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_items(
-    const Params P, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ item_start,
-    const Entry* __restrict__ ent, const float* __restrict__ desc, uint32_t* __restrict__ ctr,
-    float* __restrict__ pyr, uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey,
-    float* __restrict__ kgam, uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey,
-    float* __restrict__ pgam) {
-  __shared__ uint32_t s_item;
-  __shared__ uint32_t hist[TP];
+    const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
+    const Entry* __restrict__ ent, const float* __restrict__ desc, float* __restrict__ pyr,
+    uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam,
+    uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey, float* __restrict__ pgam) {
+  __shared__ uint32_t hist[TP];    // sorted fragments per texel in this round, then run starts
+  __shared__ uint32_t tally[TP];   // all fragments per texel in this item
+  __shared__ uint64_t thr[TP];     // current 16th key per texel
   __shared__ uint32_t ws[4];
   __shared__ uint64_t skey[SUB_F];
   __shared__ float sgam[SUB_F];
   const int t = threadIdx.x;
-  const uint32_t total = item_start[P.NB];
-  for (;;) {
-    if (t == 0) s_item = atomicAdd(&ctr[0], 1u);
-    __syncthreads();
-    const uint32_t got = s_item;
-    __syncthreads();
-    if (got >= total) break;
-    const uint32_t it = total - 1 - got;
-    const uint32_t b = find_item_bin(item_start, P.NB, it);
-    const BinInfo bi = decode_bin(P, b);
-    const uint32_t nitems = item_start[b + 1] - item_start[b];
-    const uint32_t e0 = bin_start[b] + (it - item_start[b]) * P.item_e;
-    const uint32_t e1 = min(e0 + P.item_e, bin_start[b + 1]);
-    uint64_t kk[KEEP];
-    float kg[KEEP];
+  const uint32_t total = info[1];
+  const uint4 wk = work[blockIdx.x];  // in bounds (grid = capacity); used only if valid
+  if (blockIdx.x >= total) return;
+  const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z, it = wk.w & 0x7fffffffu;
+  const bool multi = (wk.w >> 31) != 0;
+  const BinInfo bi = decode_bin(P, b);
+  uint64_t kk[KEEP];
+  float kg[KEEP];
 #pragma unroll
-    for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
-    uint32_t n = 0;
-    for (uint32_t s0 = e0; s0 < e1; s0 += SUB_E) {
-      hist[t] = 0;
-      __syncthreads();
+  for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
+  tally[t] = 0;
+  thr[t] = KEY_NONE;
+  // entries of the current round, loaded one round ahead
+  Entry en[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q)
+    if (e0 + q * TP + t < e1) en[q] = ent[e0 + q * TP + t];
+  for (uint32_t s0 = e0; s0 < e1; s0 += SUB_E) {
+    hist[t] = 0;
+    __syncthreads();
+    uint32_t cm[EPT], rank[EPT][2];  // corner masks; 16-bit ranks, two per word
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      cm[q] = 0;
+      rank[q][0] = rank[q][1] = 0;
       Corner cs[4];
-      uint32_t cm = 0;
-      uint64_t key = 0;
-      float ia = 0.0f;
-      uint32_t rank[4] = {0, 0, 0, 0};
-      if (s0 + t < e1) {
-        const Entry e = ent[s0 + t];
-        cm = entry_corners(e, bi, P.ltw, cs);
-        key = (uint64_t(e.zbits) << 32) | e.idx;
-        ia = e.ia;
+      if (s0 + q * TP + t < e1) cm[q] = entry_corners(en[q], bi, P.ltw, cs);
+      const uint64_t key = (uint64_t(en[q].zbits) << 32) | en[q].idx;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if ((cm >> q) & 1u) rank[q] = atomicAdd(&hist[cs[q].p], 1u);
+      for (int c = 0; c < 4; ++c) {
+        if ((cm[q] >> c) & 1u) {
+          const int px = cs[c].p;
+          atomicAdd(&tally[px], 1u);
+          if (key < thr[px]) rank[q][c >> 1] |= atomicAdd(&hist[px], 1u) << ((c & 1) * 16);
+          else cm[q] &= ~(1u << c);
+        }
       }
-      __syncthreads();
-      uint32_t cnt = hist[t], tot;
-      uint32_t base = block_excl_scan<4>(cnt, ws, tot);
-      __syncthreads();
-      hist[t] = base;  // reuse as the start of texel t's run
-      __syncthreads();
+    }
+    Entry nx[EPT];  // next round's entries
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if ((cm >> q) & 1u) {
-          uint32_t o = hist[cs[q].p] + rank[q];
+    for (int q = 0; q < EPT; ++q)
+      if (s0 + SUB_E + q * TP + t < e1) nx[q] = ent[s0 + SUB_E + q * TP + t];
+    __syncthreads();
+    const uint32_t cnt = hist[t];
+    uint32_t tot;
+    const uint32_t base = block_excl_scan<4>(cnt, ws, tot);
+    hist[t] = base;  // all counts were read before the scan's first barrier
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      if (!cm[q]) continue;
+      Corner cs[4];
+      entry_corners(en[q], bi, P.ltw, cs);
+      const uint64_t key = (uint64_t(en[q].zbits) << 32) | en[q].idx;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if ((cm[q] >> c) & 1u) {
+          const uint32_t o = hist[cs[c].p] + ((rank[q][c >> 1] >> ((c & 1) * 16)) & 0xffffu);
           skey[o] = key;
-          sgam[o] = (cs[q].wx * cs[q].wy) * ia;
+          sgam[o] = (cs[c].wx * cs[c].wy) * en[q].ia;
         }
-      __syncthreads();
-      for (uint32_t r = 0; r < cnt; ++r) top_insert(kk, kg, skey[base + r], sgam[base + r]);
-      n += cnt;
-      __syncthreads();
     }
-    if (nitems == 1) {
-      finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam);
-    } else {
-      pcnt[size_t(it) * TP + t] = n;
-      const uint32_t k = min(n, uint32_t(KEEP));
+    __syncthreads();
+    for (uint32_t r = 0; r < cnt; ++r) top_insert(kk, kg, skey[base + r], sgam[base + r]);
+    thr[t] = kk[KEEP - 1];
 #pragma unroll
-      for (int m = 0; m < KEEP; ++m)
-        if (uint32_t(m) < k) {
-          pkey[(size_t(it) * KEEP + m) * TP + t] = kk[m];
-          pgam[(size_t(it) * KEEP + m) * TP + t] = kg[m];
-        }
-    }
+    for (int q = 0; q < EPT; ++q) en[q] = nx[q];
+    __syncthreads();
+  }
+  const uint32_t n = tally[t];
+  if (!multi) {
+    finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam, t);
+  } else {
+    // partial list of this texel: 16 keys and gammas stored contiguously (unused slots hold
+    // KEY_NONE), read back as whole lists by the merge
+    pcnt[size_t(it) * TP + t] = n;
+    uint4* pk = reinterpret_cast<uint4*>(pkey + (size_t(it) * TP + t) * KEEP);
+    float4* pg = reinterpret_cast<float4*>(pgam + (size_t(it) * TP + t) * KEEP);
+#pragma unroll
+    for (int m = 0; m < KEEP; m += 2)
+      pk[m / 2] = make_uint4(uint32_t(kk[m]), uint32_t(kk[m] >> 32), uint32_t(kk[m + 1]),
+                             uint32_t(kk[m + 1] >> 32));
+#pragma unroll
+    for (int m = 0; m < KEEP; m += 4) pg[m / 4] = make_float4(kg[m], kg[m + 1], kg[m + 2], kg[m + 3]);
   }
 }
 
-// fwd_merge: bins that were cut into several items merge their partial top-16 lists.
+// Compare-exchange of (key, gamma) pairs: afterwards a holds the smaller key.
+__device__ __forceinline__ void cswap(uint64_t& ka, float& ga, uint64_t& kb, float& gb) {
+  const bool sw = kb < ka;
+  const uint64_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+  const float g0 = sw ? gb : ga, g1 = sw ? ga : gb;
+  ka = k0; kb = k1; ga = g0; gb = g1;
+}
+
+// Lowest 16 of two ascending lists: c[i] = min(a[i], b[15-i]) is bitonic and holds them;
+// half-cleaners of width 8, 4, 2, 1 sort it.
+__device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
+                                        const uint64_t (&ok)[KEEP], const float (&og)[KEEP]) {
+#pragma unroll
+  for (int i = 0; i < KEEP; ++i) {
+    const bool take = ok[KEEP - 1 - i] < k[i];
+    k[i] = take ? ok[KEEP - 1 - i] : k[i];
+    g[i] = take ? og[KEEP - 1 - i] : g[i];
+  }
+#pragma unroll
+  for (int w = KEEP / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int i = 0; i < KEEP; ++i)
+      if ((i & w) == 0) cswap(k[i], g[i], k[i + w], g[i + w]);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor(uint32_t(v), m, 64);
+  const uint32_t hi = __shfl_xor(uint32_t(v >> 32), m, 64);
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// fwd_merge: bins that were cut into several items.  A workgroup takes 64 texels of one
+// such bin; its four wavefronts each merge every fourth item's partial lists (thread =
+// texel; each list is read whole with independent loads), the four results are combined
+// through LDS and the first wavefront blends.  Work units (bin, 64 texels) are strided over
+// the grid.
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_merge(
-    const Params P, const uint32_t* __restrict__ item_start, const uint32_t* __restrict__ pcnt,
+    const Params P, const uint32_t* __restrict__ item_start, const uint32_t* __restrict__ multi_bins,
+    const uint32_t* __restrict__ info, const uint32_t* __restrict__ pcnt,
     const uint64_t* __restrict__ pkey, const float* __restrict__ pgam,
     const float* __restrict__ desc, float* __restrict__ pyr, uint32_t* __restrict__ npix,
     uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
-  const int t = threadIdx.x;
-  for (uint32_t b = blockIdx.x; b < P.NB; b += gridDim.x) {
+  __shared__ uint64_t s_key[3][KEEP][64];
+  __shared__ float s_gam[3][KEEP][64];
+  __shared__ uint32_t s_n[3][64];
+  const uint32_t units = info[3] * (TP / 64);
+  const int lane = threadIdx.x & 63;
+  const int slice = threadIdx.x >> 6;
+  for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t b = multi_bins[u / (TP / 64)];
+    const int t = int(u % (TP / 64)) * 64 + lane;  // texel
     const uint32_t i0 = item_start[b], i1 = item_start[b + 1];
-    if (i1 - i0 <= 1) continue;
-    const BinInfo bi = decode_bin(P, b);
     uint64_t kk[KEEP];
     float kg[KEEP];
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
     uint32_t n = 0;
-    for (uint32_t it = i0; it < i1; ++it) {
-      const uint32_t c = pcnt[size_t(it) * TP + t];
-      n += c;
-      const uint32_t k = min(c, uint32_t(KEEP));
-      for (uint32_t m = 0; m < k; ++m) {
-        const uint64_t key = pkey[(size_t(it) * KEEP + m) * TP + t];
-        if (!(key < kk[KEEP - 1])) break;  // partial lists are sorted
-        top_insert(kk, kg, key, pgam[(size_t(it) * KEEP + m) * TP + t]);
+    for (uint32_t it = i0 + slice; it < i1; it += 4) {
+      n += pcnt[size_t(it) * TP + t];
+      // a partial list holds min(count, 16) ascending keys, then KEY_NONE
+      const uint4* pk = reinterpret_cast<const uint4*>(pkey + (size_t(it) * TP + t) * KEEP);
+      const float4* pg = reinterpret_cast<const float4*>(pgam + (size_t(it) * TP + t) * KEEP);
+      uint64_t ok[KEEP];
+      float og[KEEP];
+#pragma unroll
+      for (int m = 0; m < KEEP; m += 2) {
+        const uint4 v = pk[m / 2];
+        ok[m] = (uint64_t(v.y) << 32) | v.x;
+        ok[m + 1] = (uint64_t(v.w) << 32) | v.z;
       }
+#pragma unroll
+      for (int m = 0; m < KEEP; m += 4) {
+        const float4 v = pg[m / 4];
+        og[m] = v.x; og[m + 1] = v.y; og[m + 2] = v.z; og[m + 3] = v.w;
+      }
+      merge16(kk, kg, ok, og);
     }
-    finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam);
+    if (slice > 0) {
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) {
+        s_key[slice - 1][m][lane] = kk[m];
+        s_gam[slice - 1][m][lane] = kg[m];
+      }
+      s_n[slice - 1][lane] = n;
+    }
+    __syncthreads();
+    if (slice == 0) {
+#pragma unroll 1
+      for (int q = 0; q < 3; ++q) {
+        uint64_t ok[KEEP];
+        float og[KEEP];
+#pragma unroll
+        for (int m = 0; m < KEEP; ++m) { ok[m] = s_key[q][m][lane]; og[m] = s_gam[q][m][lane]; }
+        merge16(kk, kg, ok, og);
+        n += s_n[q][lane];
+      }
+      finalize_texel<D>(P, decode_bin(P, b), b, kk, kg, n, desc, pyr, npix, kkey, kgam, t);
+    }
+    __syncthreads();  // LDS is reused by the next unit
   }
 }
 
@@ -660,8 +798,8 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
                                                     const float* __restrict__ desc,
                                                     const float* __restrict__ gpyr,
                                                     float2* __restrict__ bst) {
-  const uint32_t b = blockIdx.x;
   const int t = threadIdx.x;
+  const uint32_t b = blockIdx.x;
   const uint32_t n = npix[size_t(b) * TP + t];
   if (n == 0) return;
   const BinInfo bi = decode_bin(P, b);
@@ -678,24 +816,40 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
   }
   const uint32_t k = min(n, uint32_t(KEEP));
   float gam[KEEP], Tm[KEEP], gm[KEEP];
+  uint32_t idx[KEEP];
+  // kept entries first (independent loads), then the descriptor gathers in batches
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    const size_t ko = (size_t(b) * KEEP + m) * TP + t;
+    const bool v = uint32_t(m) < k;
+    idx[m] = v ? uint32_t(kkey[ko]) : 0u;
+    gam[m] = v ? kgam[ko] : 0.0f;
+  }
   float T = 1.0f;
 #pragma unroll
   for (int m = 0; m < KEEP; ++m) {
-    gam[m] = 0.0f; Tm[m] = 0.0f; gm[m] = 0.0f;
-    if (uint32_t(m) < k) {
-      const size_t ko = (size_t(b) * KEEP + m) * TP + t;
-      const uint32_t idx = uint32_t(kkey[ko]);
-      gam[m] = kgam[ko];
-      Tm[m] = T;
-      T = T * (1.0f - gam[m]);
-      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx) * D);
+    Tm[m] = T;
+    if (uint32_t(m) < k) T = T * (1.0f - gam[m]);
+  }
+  constexpr int GB = D > 4 ? 4 : 8;
+#pragma unroll
+  for (int m0 = 0; m0 < KEEP; m0 += GB) {
+    float4 tv[GB][D / 4];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx[m0 + q]) * D);
+#pragma unroll
+      for (int r = 0; r < D / 4; ++r)
+        tv[q][r] = uint32_t(m0 + q) < k ? tp[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
       float acc = 0.0f;
 #pragma unroll
-      for (int q = 0; q < D / 4; ++q) {
-        float4 tv = tp[q];
-        acc += G[4 * q] * tv.x + G[4 * q + 1] * tv.y + G[4 * q + 2] * tv.z + G[4 * q + 3] * tv.w;
-      }
-      gm[m] = acc;
+      for (int r = 0; r < D / 4; ++r)
+        acc += G[4 * r] * tv[q][r].x + G[4 * r + 1] * tv[q][r].y + G[4 * r + 2] * tv[q][r].z +
+               G[4 * r + 3] * tv[q][r].w;
+      gm[m0 + q] = acc;
     }
   }
   float B = 0.0f;
@@ -712,93 +866,95 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
 // bwd_items: per work item, each entry finds its corners in the tile's kept lists and writes
 // its partial-gradient row: (A, Bx, By, 0, tau[D]) with A = sum dgamma wx wy,
 // Bx = sum dgamma sx wy, By = sum dgamma wx sy, tau = sum T_m gamma_m G over its corners.
+// A corner is kept iff its key is not above the texel's last kept key (the kept set is the
+// 16 smallest keys); its position among the kept is found by point index.
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_items(
-    const Params P, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ item_start,
-    const Entry* __restrict__ ent, const uint32_t* __restrict__ npix,
-    const uint64_t* __restrict__ kkey, const float2* __restrict__ bst,
-    const float* __restrict__ gpyr, uint32_t* __restrict__ ctr, float* __restrict__ rows) {
+    const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
+    const Entry* __restrict__ ent,
+    const uint32_t* __restrict__ npix, const uint64_t* __restrict__ kkey,
+    const float2* __restrict__ bst, const float* __restrict__ gpyr, float* __restrict__ rows) {
   constexpr int RW = 4 + D;
-  __shared__ uint32_t s_item;
   __shared__ uint32_t s_k[TP];
-  __shared__ uint64_t s_key[KEEP][TP];
-  __shared__ float2 s_bst[KEEP][TP];
+  __shared__ uint64_t s_last[TP];
+  __shared__ uint32_t s_idx[KEEP][TP];
   __shared__ float s_G[TP][D + 1];
   const int t = threadIdx.x;
-  const uint32_t total = item_start[P.NB];
-  uint32_t loaded = ~0u;
-  for (;;) {
-    if (t == 0) s_item = atomicAdd(&ctr[1], 1u);
-    __syncthreads();
-    const uint32_t got = s_item;
-    __syncthreads();
-    if (got >= total) break;
-    const uint32_t it = total - 1 - got;
-    const uint32_t b = find_item_bin(item_start, P.NB, it);
-    const BinInfo bi = decode_bin(P, b);
-    const int lth = 8 - P.ltw;
-    if (b != loaded) {  // stage the tile's kept lists, blend adjoints and upstream gradient
-      const uint32_t n = npix[size_t(b) * TP + t];
-      const uint32_t k = min(n, uint32_t(KEEP));
-      s_k[t] = k;
+  const uint32_t total = info[1];
+  const uint4 wk = work[blockIdx.x];
+  if (blockIdx.x >= total) return;
+  const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z;
+  const BinInfo bi = decode_bin(P, b);
+  const int lth = 8 - P.ltw;
+  {  // stage the tile's kept point ids, last kept keys and upstream gradient
+    const uint32_t n = npix[size_t(b) * TP + t];
+    const uint32_t k = min(n, uint32_t(KEEP));
+    s_k[t] = k;
+    uint64_t last = 0;
 #pragma unroll
-      for (int m = 0; m < KEEP; ++m) {
-        if (uint32_t(m) < k) {
-          s_key[m][t] = kkey[(size_t(b) * KEEP + m) * TP + t];
-          s_bst[m][t] = bst[(size_t(b) * KEEP + m) * TP + t];
-        } else {
-          s_key[m][t] = KEY_NONE;
-        }
+    for (int m = 0; m < KEEP; ++m)
+      if (uint32_t(m) < k) {
+        const uint64_t key = kkey[(size_t(b) * KEEP + m) * TP + t];
+        s_idx[m][t] = uint32_t(key);
+        last = key;
       }
-      const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
-      const int j = (bi.ty << lth) + (t >> P.ltw);
-      if (i < bi.WL && j < bi.HL && k > 0) {
-        const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+    s_last[t] = last;
+    const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+    const int j = (bi.ty << lth) + (t >> P.ltw);
+    if (k > 0) {  // texels with fragments lie inside the layer
+      const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
 #pragma unroll
-        for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
-      } else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) s_G[t][d] = 0.0f;
-      }
-      loaded = b;
-      __syncthreads();
+      for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
     }
-    const uint32_t e0 = bin_start[b] + (it - item_start[b]) * P.item_e;
-    const uint32_t e1 = min(e0 + P.item_e, bin_start[b + 1]);
-    for (uint32_t e = e0 + t; e < e1; e += TP) {
-      const Entry en = ent[e];
-      Corner cs[4];
-      const uint32_t cm = entry_corners(en, bi, P.ltw, cs);
-      const uint64_t key = (uint64_t(en.zbits) << 32) | en.idx;
-      float A = 0.0f, Bx = 0.0f, By = 0.0f;
-      float tau[D];
+  }
+  __syncthreads();
+  Entry nxt;
+  if (e0 + t < e1) nxt = ent[e0 + t];
+  for (uint32_t e = e0 + t; e < e1; e += TP) {
+    const Entry en = nxt;
+    if (e + TP < e1) nxt = ent[e + TP];  // prefetch the next entry of this thread
+    Corner cs[4];
+    uint32_t cm = entry_corners(en, bi, P.ltw, cs);
+    const uint64_t key = (uint64_t(en.zbits) << 32) | en.idx;
+    size_t pos[4];
 #pragma unroll
-      for (int d = 0; d < D; ++d) tau[d] = 0.0f;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!((cm >> q) & 1u)) continue;
-        const int p = cs[q].p;
-        const uint32_t kp = s_k[p];
-        if (kp == 0 || key > s_key[kp - 1][p]) continue;  // not among the kept fragments
-        uint32_t m = 0;
-        while (m < kp && s_key[m][p] != key) ++m;
-        if (m == kp) continue;
-        const float2 st = s_bst[m][p];
-        const float dg = st.x;
-        A += dg * (cs[q].wx * cs[q].wy);
-        Bx += dg * (cs[q].sx * cs[q].wy);
-        By += dg * (cs[q].wx * cs[q].sy);
-#pragma unroll
-        for (int d = 0; d < D; ++d) tau[d] += st.y * s_G[p][d];
+    for (int q = 0; q < 4; ++q) {
+      pos[q] = 0;
+      if (!((cm >> q) & 1u)) continue;
+      const int p = cs[q].p;
+      const uint32_t kp = s_k[p];
+      uint32_t m = kp;
+      if (kp != 0 && !(key > s_last[p])) {  // among the kept fragments: find its position
+        m = 0;
+        while (m < kp && s_idx[m][p] != en.idx) ++m;
       }
-      float* r = rows + ((size_t(bi.v) * NSLOT + en.slot) * size_t(P.n) + en.idx) * RW;
-      float4* r4 = reinterpret_cast<float4*>(r);
-      r4[0] = make_float4(A, Bx, By, 0.0f);
-#pragma unroll
-      for (int q = 0; q < D / 4; ++q)
-        r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
+      if (m == kp) cm &= ~(1u << q);
+      else pos[q] = (size_t(b) * KEEP + m) * TP + uint32_t(p);
     }
-    __syncthreads();  // the next item may restage the tables
+    float2 st[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st[q] = ((cm >> q) & 1u) ? bst[pos[q]] : make_float2(0.f, 0.f);
+    float A = 0.0f, Bx = 0.0f, By = 0.0f;
+    float tau[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) tau[d] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((cm >> q) & 1u)) continue;
+      const int p = cs[q].p;
+      const float dg = st[q].x;
+      A += dg * (cs[q].wx * cs[q].wy);
+      Bx += dg * (cs[q].sx * cs[q].wy);
+      By += dg * (cs[q].wx * cs[q].sy);
+#pragma unroll
+      for (int d = 0; d < D; ++d) tau[d] += st[q].y * s_G[p][d];
+    }
+    float* r = rows + ((size_t(bi.v) * NSLOT + en.slot) * size_t(P.n) + en.idx) * RW;
+    float4* r4 = reinterpret_cast<float4*>(r);
+    r4[0] = make_float4(A, Bx, By, 0.0f);
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q)
+      r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
   }
 }
 
@@ -885,11 +1041,11 @@ thread_local int32_t g_last_hip = 0;
 
 // Optional per-kernel timing (reports only): a start and an end event around every kernel
 // launch, on the launch stream; read back and summed per stage by trips_timing_read.
-enum Stage { ST_FILL_F, ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_SCATTER, ST_FWD_ITEMS, ST_FWD_MERGE,
-             ST_FILL_B, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_POINTS, ST_EXPORT, NUM_STAGES };
+enum Stage { ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_ITEM_BINS, ST_SCATTER, ST_FWD_ITEMS,
+             ST_FWD_MERGE, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_POINTS, ST_EXPORT, NUM_STAGES };
 const char* const kStageNames[NUM_STAGES] = {
-    "fill_fwd", "count", "colscan", "binscan", "scatter", "fwd_items", "fwd_merge",
-    "fill_bwd", "bwd_pixels", "bwd_items", "bwd_points", "export"};
+    "count", "colscan", "binscan", "item_bins", "scatter", "fwd_items", "fwd_merge",
+    "bwd_pixels", "bwd_items", "bwd_points", "export"};
 static_assert(NUM_STAGES == TRIPS_NUM_STAGES, "stage table");
 
 struct TimingState {
@@ -934,12 +1090,20 @@ struct Layout {
   uint64_t icap;      // work-item capacity
   uint64_t npyr;      // texels of all views and layers
   // saved buffer
-  size_t s_info, s_bin_start, s_item_start, s_npix, s_kkey, s_kgam, s_ent, saved_bytes;
+  size_t s_info, s_bin_start, s_item_start, s_multi, s_npix, s_kkey, s_kgam, s_tables_end, s_work, s_ent;
+  size_t saved_bytes;
   // workspace
-  size_t w_ctr, w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, ws_bytes;
+  size_t w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, ws_bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// The binning passes keep a 16-bit counter per tile of one view in LDS (at most 64 KB);
+// the scatter pass also stages a 32-bit base per tile when both tables fit in 150 KB.
+constexpr uint32_t kMaxViewBins = 32768;
+constexpr size_t kLdsLimit = 150 * 1024;
+size_t count_lds(uint32_t nbins) { return size_t((nbins + 1) / 2) * 4; }
+size_t staged_scatter_lds(uint32_t nbins) { return size_t((nbins + 1) / 2 + nbins) * 4; }
 
 trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int32_t views,
                          int64_t n, const trips_tuning* tun, Layout& lay) {
@@ -997,7 +1161,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
     vp.lbin[P.nl] = uint32_t(bins + vb);
     vp.nbins = uint32_t(vb);
     bins += vb;
-    if (vb > 32768) return TRIPS_ERR_UNSUPPORTED;  // LDS histogram of one view (64 KB)
+    if (vb > kMaxViewBins) return TRIPS_ERR_UNSUPPORTED;  // LDS tables of one view
     lay.nbv_max = std::max<uint32_t>(lay.nbv_max, uint32_t(vb));
     if (bins >= (1ull << 31) / TP || texels >= (1ull << 32)) return TRIPS_ERR_CAPACITY;
   }
@@ -1013,13 +1177,17 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.s_info = take(64 * 4);
   lay.s_bin_start = take((NB + 1) * 4);
   lay.s_item_start = take((NB + 1) * 4);
+  lay.s_multi = take(NB * 4);
+  // texel tables: their offsets depend only on the cameras and config (export reads them)
   lay.s_npix = take(NB * TP * 4);
   lay.s_kkey = take(NB * TP * KEEP * 8);
   lay.s_kgam = take(NB * TP * KEEP * 4);
+  lay.s_tables_end = o;
+  // point-count dependent parts
+  lay.s_work = take(size_t(lay.icap) * sizeof(uint4));
   lay.s_ent = take(size_t(lay.ecap) * sizeof(Entry));
   lay.saved_bytes = o;
   o = 0;
-  lay.w_ctr = take(64 * 4);
   const size_t scratch = o;
   // forward scratch
   lay.w_H = take(size_t(P.nblk) * NB * 4);
@@ -1042,17 +1210,6 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
     if (e_ != hipSuccess) { g_last_hip = int32_t(e_); return TRIPS_ERR_HIP; } \
   } while (0)
 
-int persistent_grid() {
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-  }
-  return cus * 8;
-}
-
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -1069,7 +1226,6 @@ template <int D>
 trips_status launch_forward(const Layout& lay, const trips_points& pts, float* pyr, char* sv,
                             char* ws, hipStream_t st) {
   const Params& P = lay.P;
-  uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + lay.w_ctr);
   uint32_t* H = reinterpret_cast<uint32_t*>(ws + lay.w_H);
   uint32_t* tot = reinterpret_cast<uint32_t*>(ws + lay.w_tot);
   uint32_t* pcnt = reinterpret_cast<uint32_t*>(ws + lay.w_pcnt);
@@ -1078,58 +1234,64 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   uint32_t* info = reinterpret_cast<uint32_t*>(sv + lay.s_info);
   uint32_t* bin_start = reinterpret_cast<uint32_t*>(sv + lay.s_bin_start);
   uint32_t* item_start = reinterpret_cast<uint32_t*>(sv + lay.s_item_start);
+  uint4* work = reinterpret_cast<uint4*>(sv + lay.s_work);
+  uint32_t* multi_bins = reinterpret_cast<uint32_t*>(sv + lay.s_multi);
   uint32_t* npix = reinterpret_cast<uint32_t*>(sv + lay.s_npix);
   uint64_t* kkey = reinterpret_cast<uint64_t*>(sv + lay.s_kkey);
   float* kgam = reinterpret_cast<float*>(sv + lay.s_kgam);
   Entry* ent = reinterpret_cast<Entry*>(sv + lay.s_ent);
-  const size_t lds = size_t((lay.nbv_max + 1) / 2) * 4;
 
-  {
-    StageTimer tm(ST_FILL_F, st);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ctr, 64u, 0u);
-  }
-  TRIPS_HIP(hipGetLastError());
   if (P.nblk > 0) {
     StageTimer tm(ST_COUNT, st);
-    hipLaunchKernelGGL(k_count, dim3(P.nblk * P.V), dim3(256), lds, st, P, pts.x, pts.y, pts.z,
-                       pts.size_w, H);
-    TRIPS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_count, dim3(P.nblk * P.V), dim3(BIN_THREADS), count_lds(lay.nbv_max), st,
+                       P, pts.x, pts.y, pts.z, pts.size_w, H);
   }
-  if (P.NB > 0) {
+  TRIPS_HIP(hipGetLastError());
+  {
     StageTimer tm(ST_COLSCAN, st);
-    if (P.nblk > 0) {
-      hipLaunchKernelGGL(k_colscan, dim3((P.NB + 63) / 64), dim3(256), 0, st, H, tot, P.NB, P.nblk);
-    } else {
+    if (P.nblk > 0)
+      hipLaunchKernelGGL(k_colscan, dim3((P.NB + 63) / 64), dim3(64 * CS_SEG), 0, st, H, tot,
+                         P.NB, P.nblk);
+    else
       hipLaunchKernelGGL(k_fill_u32, dim3((P.NB + 255) / 256), dim3(256), 0, st, tot, P.NB, 0u);
-    }
-    TRIPS_HIP(hipGetLastError());
   }
+  TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BINSCAN, st);
-    hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, tot, bin_start, item_start, info,
-                       P.NB, P.item_e);
+    hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, tot, bin_start, item_start,
+                       multi_bins, info, P.NB, P.item_e);
+  }
+  TRIPS_HIP(hipGetLastError());
+  {
+    StageTimer tm(ST_ITEM_BINS, st);
+    hipLaunchKernelGGL(k_item_bins, dim3((P.NB + 255) / 256), dim3(256), 0, st, item_start,
+                       bin_start, work, P.NB, P.item_e);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.nblk > 0) {
     StageTimer tm(ST_SCATTER, st);
-    hipLaunchKernelGGL(k_scatter, dim3(P.nblk * P.V), dim3(256), lds, st, P, pts.x, pts.y, pts.z,
-                       pts.size_w, pts.opacity, H, bin_start, ent, info);
-    TRIPS_HIP(hipGetLastError());
-  }
-  const int grid = int(std::min<uint64_t>(lay.icap, uint64_t(persistent_grid())));
-  {
-    StageTimer tm(ST_FWD_ITEMS, st);
-    hipLaunchKernelGGL(k_fwd_items<D>, dim3(grid), dim3(256), 0, st, P, bin_start, item_start,
-                       ent, pts.desc, ctr, pyr, npix, kkey, kgam, pcnt, pkey, pgam);
+    if (staged_scatter_lds(lay.nbv_max) <= kLdsLimit)
+      hipLaunchKernelGGL(k_scatter<true>, dim3(P.nblk * P.V), dim3(BIN_THREADS),
+                         staged_scatter_lds(lay.nbv_max), st, P, pts.x, pts.y, pts.z, pts.size_w,
+                         pts.opacity, H, bin_start, ent, info);
+    else
+      hipLaunchKernelGGL(k_scatter<false>, dim3(P.nblk * P.V), dim3(BIN_THREADS),
+                         count_lds(lay.nbv_max), st, P, pts.x, pts.y, pts.z, pts.size_w,
+                         pts.opacity, H, bin_start, ent, info);
   }
   TRIPS_HIP(hipGetLastError());
-  const int mgrid = int(std::min<uint32_t>(P.NB, 2048u));
-  if (mgrid > 0) {
-    StageTimer tm(ST_FWD_MERGE, st);
-    hipLaunchKernelGGL(k_fwd_merge<D>, dim3(mgrid), dim3(256), 0, st, P, item_start, pcnt, pkey,
-                       pgam, pts.desc, pyr, npix, kkey, kgam);
-    TRIPS_HIP(hipGetLastError());
+  {  // one workgroup per work item; workgroups beyond the item count exit at once
+    StageTimer tm(ST_FWD_ITEMS, st);
+    hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info, work,
+                       ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam);
   }
+  TRIPS_HIP(hipGetLastError());
+  {
+    StageTimer tm(ST_FWD_MERGE, st);
+    hipLaunchKernelGGL(k_fwd_merge<D>, dim3(1024), dim3(256), 0, st, P, item_start, multi_bins,
+                       info, pcnt, pkey, pgam, pts.desc, pyr, npix, kkey, kgam);
+  }
+  TRIPS_HIP(hipGetLastError());
   return TRIPS_OK;
 }
 
@@ -1138,40 +1300,33 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
                              const char* sv, char* ws, float* gx, float* gy, float* gz, float* gsw,
                              float* ga, float* gd, hipStream_t st) {
   const Params& P = lay.P;
-  uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + lay.w_ctr);
   float2* bst = reinterpret_cast<float2*>(ws + lay.w_bst);
   float* rows = reinterpret_cast<float*>(ws + lay.w_rows);
-  const uint32_t* bin_start = reinterpret_cast<const uint32_t*>(sv + lay.s_bin_start);
-  const uint32_t* item_start = reinterpret_cast<const uint32_t*>(sv + lay.s_item_start);
+  const uint32_t* info = reinterpret_cast<const uint32_t*>(sv + lay.s_info);
+  const uint4* work = reinterpret_cast<const uint4*>(sv + lay.s_work);
   const uint32_t* npix = reinterpret_cast<const uint32_t*>(sv + lay.s_npix);
   const uint64_t* kkey = reinterpret_cast<const uint64_t*>(sv + lay.s_kkey);
   const float* kgam = reinterpret_cast<const float*>(sv + lay.s_kgam);
   const Entry* ent = reinterpret_cast<const Entry*>(sv + lay.s_ent);
 
   {
-    StageTimer tm(ST_FILL_B, st);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ctr, 64u, 0u);
-  }
-  TRIPS_HIP(hipGetLastError());
-  if (P.NB > 0) {
     StageTimer tm(ST_BWD_PIXELS, st);
     hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, npix, kkey, kgam, pts.desc,
                        gpyr, bst);
-    TRIPS_HIP(hipGetLastError());
   }
-  const int grid = int(std::min<uint64_t>(lay.icap, uint64_t(persistent_grid() / 2)));
+  TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BWD_ITEMS, st);
-    hipLaunchKernelGGL(k_bwd_items<D>, dim3(grid), dim3(256), 0, st, P, bin_start, item_start,
-                       ent, npix, kkey, bst, gpyr, ctr, rows);
+    hipLaunchKernelGGL(k_bwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info, work,
+                       ent, npix, kkey, bst, gpyr, rows);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.n > 0) {
     StageTimer tm(ST_BWD_POINTS, st);
     hipLaunchKernelGGL(k_bwd_points<D>, dim3(uint32_t((P.n + 255) / 256)), dim3(256), 0, st, P,
                        pts.x, pts.y, pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd);
-    TRIPS_HIP(hipGetLastError());
   }
+  TRIPS_HIP(hipGetLastError());
   return TRIPS_OK;
 }
 
@@ -1313,7 +1468,7 @@ trips_status trips_export_fragments(const trips_config* cfg, const trips_camera*
   if (s != TRIPS_OK) return s;
   if (!saved || !aligned(saved) || !counts || !ids) return TRIPS_ERR_INVALID_ARG;
   // the texel tables do not depend on n; only their part of `saved` is read
-  if (saved_bytes < lay.s_ent) return TRIPS_ERR_WORKSPACE;
+  if (saved_bytes < lay.s_tables_end) return TRIPS_ERR_WORKSPACE;
   const char* sv = static_cast<const char*>(saved);
   if (lay.P.NB > 0) {
     StageTimer tm(ST_EXPORT, st);
@@ -1342,6 +1497,57 @@ trips_status trips_forward_stats(const trips_config* cfg, const trips_camera* ca
   stats[2] = lay.P.NB;
   stats[3] = info[2];
   return TRIPS_OK;
+}
+
+trips_status trips_autotune(const trips_config* cfg, const trips_points* pts,
+                            const trips_camera* cams, int32_t views,
+                            const trips_tuning* candidates, int32_t ncand, int32_t reps,
+                            float* pyr, void* saved, size_t saved_bytes, void* ws,
+                            size_t ws_bytes, const float* gpyr, float* gx, float* gy, float* gz,
+                            float* gsw, float* ga, float* gd, trips_tuning* best,
+                            float* ms_host, hipStream_t st) {
+  if (!candidates || ncand < 1 || reps < 1 || !best || !ms_host) return TRIPS_ERR_INVALID_ARG;
+  // validate every candidate before launching anything
+  for (int c = 0; c < ncand; ++c) {
+    Layout lay;
+    trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, &candidates[c], lay);
+    if (s != TRIPS_OK) return s;
+    if ((s = check_points(pts, lay)) != TRIPS_OK) return s;
+    if ((s = check_buffers(lay, saved, saved_bytes, ws, ws_bytes, true)) != TRIPS_OK) return s;
+  }
+  if (!pyr || !aligned16(pyr) || !gpyr || !aligned16(gpyr)) return TRIPS_ERR_INVALID_ARG;
+  if (pts->n > 0 && (!gx || !gy || !gz || !gsw || !ga || !gd || !aligned16(gd)))
+    return TRIPS_ERR_INVALID_ARG;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TRIPS_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return TRIPS_ERR_HIP; }
+  trips_status rs = TRIPS_OK;
+  float best_ms = 0.0f;
+  for (int c = 0; c < ncand && rs == TRIPS_OK; ++c) {
+    float total = 0.0f;
+    for (int r = -1; r < reps && rs == TRIPS_OK; ++r) {  // r = -1: warm-up
+      hipError_t e = hipEventRecord(e0, st);
+      if (e == hipSuccess) {
+        rs = trips_forward(cfg, pts, cams, views, &candidates[c], pyr, saved, saved_bytes, ws,
+                           ws_bytes, st);
+        if (rs == TRIPS_OK)
+          rs = trips_backward(cfg, pts, cams, views, &candidates[c], gpyr, saved, saved_bytes, ws,
+                              ws_bytes, gx, gy, gz, gsw, ga, gd, st);
+        if (rs == TRIPS_OK) e = hipEventRecord(e1, st);
+        if (rs == TRIPS_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (rs == TRIPS_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (r >= 0) total += ms;
+      }
+      if (e != hipSuccess) { g_last_hip = int32_t(e); rs = TRIPS_ERR_HIP; }
+    }
+    if (rs != TRIPS_OK) break;
+    ms_host[c] = total / float(reps);
+    if (c == 0 || ms_host[c] < best_ms) { best_ms = ms_host[c]; *best = candidates[c]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rs;
 }
 
 trips_status trips_plan_create(const trips_config* cfg, const trips_points* pts,

@@ -104,3 +104,21 @@ def test_forward_validates_before_launch():
     assert b(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, 0, fake, sv.value, fake, ws.value,
              fake, fake, fake, fake, fake, fake, None) == -1   # null grad_pyramid
     assert L.trips_status_string(-3) == b"problem exceeds 32-bit fragment indexing"
+
+
+def test_autotune_validates_before_launch():
+    tp, L = _lib()
+    cfg = tp.make_config(5, 4)
+    cams = (tp.Camera * 1)(tp.make_camera(_cam(64, 48)))
+    fake = 1 << 20
+    pts = tp.Points(fake, fake, fake, fake, fake, fake, 100)
+    best = tp.Tuning()
+    ms = (ctypes.c_float * 2)()
+    bad = (tp.Tuning * 2)(tp.make_tuning(16), tp.make_tuning(12))  # second tile width invalid
+    st = L.trips_autotune(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, bad, 2, 1, fake, fake,
+                          1 << 30, fake, 1 << 30, fake, fake, fake, fake, fake, fake, fake,
+                          ctypes.byref(best), ms, None)
+    assert st == -1
+    assert L.trips_autotune(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, bad, 0, 1, fake, fake,
+                            1 << 30, fake, 1 << 30, fake, fake, fake, fake, fake, fake, fake,
+                            ctypes.byref(best), ms, None) == -1

@@ -80,3 +80,19 @@ def test_sixteen_mixed_views_against_oracle(gpu):
         assert np.array_equal(res[v][1], counts), v
         assert np.array_equal(res[v][2], ids), v
         assert np.all(np.abs(res[v][0] - pyr) <= 1e-5 * np.abs(pyr)), v
+
+
+def test_autotuner_picks_a_candidate(gpu, tmp_path):
+    import paper_2401_06003_amd as tp
+    sc = scenes.unit_cube(8, n=5000, W=160, H=120, nlayers=5)
+    t = to_device(sc["points"], gpu)
+    cands = [(16, 4096, 4096), (32, 1024, 2048), (8, 2048, 8192)]
+    cache = str(tmp_path / "tune.json")
+    best, ms = tp.autotune(sc["cams"], sc["nlayers"], sc["D"], *[t[k] for k in PARAMS],
+                           candidates=cands, reps=2, cache_path=cache, device=gpu)
+    chosen = (best.tile_w, best.points_per_block, best.item_entries)
+    assert chosen in cands and all(v > 0 for v in ms.values())
+    assert chosen == min(ms, key=ms.get)
+    again, _ = tp.autotune(sc["cams"], sc["nlayers"], sc["D"], *[t[k] for k in PARAMS],
+                           candidates=cands, reps=2, cache_path=cache, device=gpu)  # from cache
+    assert (again.tile_w, again.points_per_block, again.item_entries) == chosen
