@@ -230,16 +230,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* ws, ui
 __device__ __forceinline__ void top_insert(uint64_t (&k)[KEEP], float (&g)[KEEP], uint64_t nk,
                                            float ng) {
   if (!(nk < k[KEEP - 1])) return;
+  // b[i] = nk < k[i] is false below the insertion point and true from it on: slot i takes
+  // k[i-1] if b[i-1], nk if only b[i], and keeps k[i] otherwise
+  bool b[KEEP];
+#pragma unroll
+  for (int i = 0; i < KEEP; ++i) b[i] = nk < k[i];
 #pragma unroll
   for (int i = KEEP - 1; i > 0; --i) {
-    bool up = nk < k[i - 1];
-    uint64_t ki = up ? k[i - 1] : nk;
-    float gi = up ? g[i - 1] : ng;
-    bool here = nk < k[i];
-    k[i] = here ? ki : k[i];
-    g[i] = here ? gi : g[i];
+    const uint64_t ki = b[i - 1] ? k[i - 1] : nk;
+    const float gi = b[i - 1] ? g[i - 1] : ng;
+    k[i] = b[i] ? ki : k[i];
+    g[i] = b[i] ? gi : g[i];
   }
-  if (nk < k[0]) { k[0] = nk; g[0] = ng; }
+  k[0] = b[0] ? nk : k[0];
+  g[0] = b[0] ? ng : g[0];
 }
 
 // ------------------------------------------------------------------------------------
@@ -642,7 +646,19 @@ __global__ __launch_bounds__(256) void k_fwd_items(
         }
     }
     __syncthreads();
-    for (uint32_t r = 0; r < cnt; ++r) top_insert(kk, kg, skey[base + r], sgam[base + r]);
+    // the texel's run, read from LDS four fragments at a time
+    for (uint32_t r = 0; r < cnt; r += 4) {
+      uint64_t rk[4];
+      float rg[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool v = r + q < cnt;
+        rk[q] = v ? skey[base + r + q] : KEY_NONE;
+        rg[q] = v ? sgam[base + r + q] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) top_insert(kk, kg, rk[q], rg[q]);
+    }
     thr[t] = kk[KEEP - 1];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) en[q] = nx[q];
@@ -877,7 +893,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   constexpr int RW = 4 + D;
   __shared__ uint32_t s_k[TP];
   __shared__ uint64_t s_last[TP];
-  __shared__ uint32_t s_idx[KEEP][TP];
+  __shared__ uint4 s_idx[TP][KEEP / 4];  // kept point ids of each texel, contiguous
   __shared__ float s_G[TP][D + 1];
   const int t = threadIdx.x;
   const uint32_t total = info[1];
@@ -891,13 +907,15 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     const uint32_t k = min(n, uint32_t(KEEP));
     s_k[t] = k;
     uint64_t last = 0;
+    uint32_t ids[KEEP];
 #pragma unroll
-    for (int m = 0; m < KEEP; ++m)
-      if (uint32_t(m) < k) {
-        const uint64_t key = kkey[(size_t(b) * KEEP + m) * TP + t];
-        s_idx[m][t] = uint32_t(key);
-        last = key;
-      }
+    for (int m = 0; m < KEEP; ++m) {
+      const uint64_t key = uint32_t(m) < k ? kkey[(size_t(b) * KEEP + m) * TP + t] : KEY_NONE;
+      ids[m] = uint32_t(key);
+      last = uint32_t(m) < k ? key : last;
+    }
+#pragma unroll
+    for (int m = 0; m < KEEP; m += 4) s_idx[t][m / 4] = make_uint4(ids[m], ids[m + 1], ids[m + 2], ids[m + 3]);
     s_last[t] = last;
     const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
     const int j = (bi.ty << lth) + (t >> P.ltw);
@@ -925,8 +943,14 @@ __global__ __launch_bounds__(256) void k_bwd_items(
       const uint32_t kp = s_k[p];
       uint32_t m = kp;
       if (kp != 0 && !(key > s_last[p])) {  // among the kept fragments: find its position
-        m = 0;
-        while (m < kp && s_idx[m][p] != en.idx) ++m;
+#pragma unroll
+        for (int j = 0; j < KEEP / 4; ++j) {
+          const uint4 v = s_idx[p][j];
+          m = (v.x == en.idx && uint32_t(4 * j) < kp) ? uint32_t(4 * j) : m;
+          m = (v.y == en.idx && uint32_t(4 * j + 1) < kp) ? uint32_t(4 * j + 1) : m;
+          m = (v.z == en.idx && uint32_t(4 * j + 2) < kp) ? uint32_t(4 * j + 2) : m;
+          m = (v.w == en.idx && uint32_t(4 * j + 3) < kp) ? uint32_t(4 * j + 3) : m;
+        }
       }
       if (m == kp) cm &= ~(1u << q);
       else pos[q] = (size_t(b) * KEEP + m) * TP + uint32_t(p);
