@@ -9,7 +9,9 @@ layer pair, trilinear write, per-texel depth sort, top-16, blend) then backward 
 for positions, world sizes, opacities and descriptors).  Synthetic, seeded inputs resident
 in HBM before the timed region.
 
-Also reported: per-kernel durations (HIP events around every launch, on its stream), the
+The timed step is the forward + backward launch sequence captured once in a HIP graph and
+replayed (the eager launch sequence is timed as well).  Also reported: per-kernel durations
+(a second timed run of eager steps with HIP events around every launch, on its stream), the
 roofline of the dominant kernel, the CPU oracle on the same workload, and the batched
 multi-view form (16 views of mixed resolution over 4M points, one graph launch per step)
 against 16 single-view launch sequences.
@@ -33,20 +35,29 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(stage, N, V, D, E, K, P, Ppad, nblk, NB):
+def kernel_bytes(stage, w):
     """Algorithmic bytes one launch of `stage` must move (reads + writes), for the report.
 
-    N points, V views, D channels, E tile entries, K kept fragments (sum of min(n, 16)),
-    P texels, Ppad texels incl. tile padding, nblk point blocks, NB tiles."""
-    ent, row = 24 * E, 4 * (4 + D) * E
+    w: workload counts.  N points, D channels, E tile entries (E_f of them in fine tiles,
+    the tiles of at most 256 entries), K kept fragments (K_f in fine tiles), NB tiles (NB_f
+    fine), I_c work items of the other tiles, P texels inside the layers, Ppad = 256 NB,
+    nblk point blocks.  Texels of a set of tiles inside the layers are counted pro rata."""
+    N, D, E, Ef, K, Kf = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"]
+    NB, NBf, Ic, P, nblk = w["NB"], w["NB_f"], w["I_c"], w["P"], w["nblk"]
+    Ppad = 256 * NB
+    Ec, Kc, NBc = E - Ef, K - Kf, NB - NBf
+    Pc, Pf = P * NBc / NB, P * NBf / NB
+    row = 4 * (4 + D)
     table = {
         "count": 16 * N + 4 * nblk * NB,
-        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + ent,
-        "fwd_items": ent + 4 * D * K + 4 * D * P + 4 * Ppad + 12 * K,
-        "bwd_pixels": 4 * Ppad + 12 * K + 4 * D * P + 4 * D * K + 8 * K,
-        "bwd_items": ent + 4 * Ppad + 16 * K + 4 * D * P + row,
-        "bwd_points": 20 * N + row + 4 * (5 + D) * N,
         "colscan": 8 * nblk * NB + 4 * NB,
+        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 24 * E,
+        "fwd_items": 24 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
+        "fwd_fine": 28 * Ef + (4 * D + 12) * Kf + 4 * 256 * NBf + 4 * D * Pf,
+        "bwd_pixels": 4 * Ppad + (12 + 4 * D + 8) * K + 4 * D * P,
+        "bwd_items": (24 + row) * Ec + 16 * Kc + Ic * 256 * (4 + 4 * D),
+        "bwd_fine": (24 + row) * Ef + 8 * Kf + 4 * D * Pf,
+        "bwd_points": 20 * N + row * E + 4 * (5 + D) * N,
     }
     return table.get(stage)
 
@@ -57,6 +68,23 @@ def step_bytes(N, Nv, D, F, K, P):
     read, kept ids saved and reloaded, pyramid write and upstream-gradient read, point
     re-read in backward, gradient write."""
     return N * 20 + Nv * 4 * D + 16 * F + 8 * K + 8 * D * P + Nv * (20 + 4 * D) + N * (20 + 4 * D)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes, each scaled by the same counter over a plain copy), or None when no
+    summary was taken on the current kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2401_06003_amd", "csrc", "trips.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        for line in open(f):
+            if line.startswith("traffic-json: "):
+                d = json.loads(line[len("traffic-json: "):])
+                if d.get("kernel") == kernel and d.get("source_sha256") == h:
+                    return d["bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(sc, G):
@@ -132,6 +160,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference for "
+                         "scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this renderer runs on one GPU; multi-GPU runs are not part of this "
@@ -140,6 +171,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}), flush=True)
+        return
 
     import paper_2401_06003_amd as tp
     import scenes
@@ -172,26 +214,48 @@ def main():
     K = int(torch.clamp(c64, max=tp.KEEP).sum().item())
     E, NB = st["entries"], st["bins"]
     P = r.texels
-    Ppad = NB * 256
     nblk = (N + 4095) // 4096
     Nv = st["visible"]  # points that wrote at least one fragment
+    tile_e, tile_k = r.tile_stats()
+    fine = tile_e <= 256
+    item_e = 8192  # default tuning
+    w = {"N": N, "D": D, "E": E, "E_f": int(tile_e[fine].sum()), "K": K,
+         "K_f": int(tile_k[fine].sum()), "NB": NB, "NB_f": int(fine.sum()),
+         "I_c": int(((tile_e[~fine].astype(np.int64) + item_e - 1) // item_e).sum()), "P": P,
+         "nblk": nblk}
 
-    log("timed %d steps" % args.steps)
+    # the step captured once in a HIP graph (forward then backward), replayed per step
+    plan = tp.Plan(r, *pargs, pyr, G, grads)
+
+    def step_graph():
+        plan.launch(forward=True, backward=True)
+
+    for _ in range(args.warmup):
+        step_graph()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    log("timed %d graph steps" % args.steps)
+    ms = timed(step_graph)
+    log("timed %d eager steps" % args.steps)
+    ms_eager = timed(step)
+    # per-kernel durations: the eager steps again, every launch bracketed by HIP events
+    log("timed %d eager steps with per-kernel events" % args.steps)
     tp.timing_enable(True)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms_events = timed(step)
     stages = tp.timing_read()
     tp.timing_enable(False)
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0}
-    dom = max((k for k in stage_ms if kernel_bytes(k, N, 1, D, E, K, P, Ppad, nblk, NB)),
-              key=lambda k: stage_ms[k])
-    dom_bytes = kernel_bytes(dom, N, 1, D, E, K, P, Ppad, nblk, NB)
+    dom = max((k for k in stage_ms if kernel_bytes(k, w)), key=lambda k: stage_ms[k])
+    dom_bytes = kernel_bytes(dom, w)
     achieved = dom_bytes / (stage_ms[dom] / 1e3) / 1e9
     sbytes = step_bytes(N, Nv, D, F, K, P)
 
@@ -203,13 +267,17 @@ def main():
         "config": {"workload": "clusters2m_1920x1080_8layers_d4_fwd_bwd", "points": N, "views": 1,
                    "width": cam["W"], "height": cam["H"], "layers": nl, "desc_dim": D},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "bytes_per_launch": dom_bytes, "ms_per_launch": stage_ms[dom]},
+        "ms_per_step_eager": ms_eager, "ms_per_step_eager_with_kernel_events": ms_events,
         "step_effective_hbm_frac": sbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "step_algorithmic_bytes": sbytes,
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "fragments": F, "kept_fragments": K, "tile_entries": E, "tiles": NB, "texels": P,
-        "visible_points": Nv,
+        "visible_points": Nv, "fine_tiles": w["NB_f"], "fine_tile_entries": w["E_f"],
+        "fine_tile_kept": w["K_f"], "work_items": w["I_c"],
+        "stage_gbps": {k: round(kernel_bytes(k, w) / (v / 1e3) / 1e9, 1)
+                       for k, v in stage_ms.items() if kernel_bytes(k, w)},
     }
     if not args.no_batched:
         log("batched vs per-view (16 views, 4M points)")

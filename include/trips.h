@@ -79,8 +79,9 @@ typedef struct {
 /* Launch-shape choices (all optional: pass NULL, or 0 in a field, for the defaults).
    tile_w is the width in texels of a screen tile (16x16 by default; tiles always hold
    256 texels: 8x32, 16x16, 32x8, 64x4).  points_per_block is the number of points one
-   binning workgroup histograms (256..65535).  item_entries is the number of tile entries
-   one sort/blend workgroup consumes before handing over to a merge (256..65536). */
+   binning workgroup histograms (256..65535, default 4096).  item_entries is the number of
+   tile entries one sort/blend workgroup consumes before handing over to a merge
+   (256..65536, default 8192). */
 typedef struct {
   int32_t tile_w;
   int32_t points_per_block;
@@ -134,12 +135,22 @@ trips_status trips_export_fragments(const trips_config* cfg_host, const trips_ca
                                     int32_t* ids, hipStream_t stream);
 
 /* Statistics of the forward call that filled `saved`, copied to host memory after a
-   stream synchronisation: stats_host[0] = tile entries, [1] = work items,
+   stream synchronisation: stats_host[0] = tile entries, [1] = work items (tile pieces of
+   at most item_entries entries, and tiles of at most 256 entries, which are rendered whole),
    [2] = tiles (bins), [3] = (point, view) pairs that wrote at least one fragment.
    For tests and reports; not needed for rendering. */
 trips_status trips_forward_stats(const trips_config* cfg_host, const trips_camera* cams_host,
                                  int32_t views, const trips_tuning* tuning_host, const void* saved,
                                  size_t saved_bytes, int64_t* stats_host, hipStream_t stream);
+
+/* Per-tile statistics of the forward call that filled `saved`, for reports: after a stream
+   synchronisation, entries_host[b] = tile entries of tile b and kept_host[b] = kept
+   fragments of its texels (sum of min(list length, 16)), for every tile b in bin order
+   (views, then layers, then tile rows).  Both host arrays hold stats_host[2] elements. */
+trips_status trips_tile_stats(const trips_config* cfg_host, const trips_camera* cams_host,
+                              int32_t views, const trips_tuning* tuning_host, const void* saved,
+                              size_t saved_bytes, uint32_t* entries_host, uint32_t* kept_host,
+                              hipStream_t stream);
 
 const char* trips_status_string(trips_status status);
 int32_t trips_last_hip_error(void);
@@ -151,7 +162,7 @@ int32_t trips_last_hip_error(void);
    milliseconds and the number of launches since the last read (or enable), then resets.
    Stage k is named by trips_stage_name(k), k < TRIPS_NUM_STAGES.  The events are host
    objects owned by the library; no device memory is allocated. */
-#define TRIPS_NUM_STAGES 11
+#define TRIPS_NUM_STAGES 13
 trips_status trips_timing_enable(int32_t enable);
 trips_status trips_timing_read(float* ms_host /*[TRIPS_NUM_STAGES]*/,
                                int32_t* launches_host /*[TRIPS_NUM_STAGES]*/);

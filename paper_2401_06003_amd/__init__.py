@@ -70,6 +70,8 @@ def lib():
                                              c_size_t, c_void_p, c_void_p, c_void_p]
         L.trips_forward_stats.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
                                           c_size_t, P(c_int64), c_void_p]
+        L.trips_tile_stats.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
+                                       c_size_t, c_void_p, c_void_p, c_void_p]
         L.trips_status_string.argtypes = [c_int32]
         L.trips_status_string.restype = ctypes.c_char_p
         L.trips_last_hip_error.restype = c_int32
@@ -89,8 +91,8 @@ def lib():
         L.trips_plan_launch.argtypes = [c_void_p, c_int32, c_void_p]
         L.trips_plan_destroy.argtypes = [c_void_p]
         for name in ("trips_layer_layout", "trips_buffer_sizes", "trips_forward", "trips_backward",
-                     "trips_export_fragments", "trips_forward_stats", "trips_plan_create",
-                     "trips_plan_launch"):
+                     "trips_export_fragments", "trips_forward_stats", "trips_tile_stats",
+                     "trips_plan_create", "trips_plan_launch"):
             getattr(L, name).restype = c_int32
         L.trips_plan_destroy.restype = None
         _lib = L
@@ -245,6 +247,19 @@ class Renderer:
                                          self.saved_bytes, st, _stream()), "trips_forward_stats")
         return {"entries": st[0], "items": st[1], "bins": st[2], "visible": st[3]}
 
+    def tile_stats(self):
+        """Per-tile (entries, kept fragments) of the last forward call, numpy uint32 arrays in
+        bin order (synchronises; for reports)."""
+        import numpy as np
+        nb = self.stats()["bins"]
+        ent = np.zeros(nb, dtype=np.uint32)
+        kept = np.zeros(nb, dtype=np.uint32)
+        _check(lib().trips_tile_stats(ctypes.byref(self.cfg), self.cams, self.V,
+                                      ctypes.byref(self.tune), _ptr(self.saved), self.saved_bytes,
+                                      ent.ctypes.data_as(c_void_p), kept.ctypes.data_as(c_void_p),
+                                      _stream()), "trips_tile_stats")
+        return ent, kept
+
     def split(self, flat):
         """Per view, per layer [H_L, W_L, D] views of a flat pyramid."""
         out, o = [], 0
@@ -257,7 +272,7 @@ class Renderer:
         return out
 
 
-NUM_STAGES = 11
+NUM_STAGES = 13
 
 
 def timing_enable(on=True):
@@ -308,7 +323,7 @@ class Plan:
 
 # Launch shapes tried by default: tile width x points per binning block x entries per item.
 DEFAULT_CANDIDATES = [(tw, pb, ie) for tw in (8, 16, 32) for pb in (4096, 8192)
-                      for ie in (2048, 4096, 8192)]
+                      for ie in (4096, 8192, 16384)]
 
 
 def autotune(cams, num_layers, desc_dim, x, y, z, sw, alpha, desc, candidates=None, reps=3,

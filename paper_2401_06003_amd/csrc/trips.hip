@@ -43,6 +43,20 @@ constexpr int NSLOT = 8;   // (layer entry 0/1) x (tile touch 0..3)
 constexpr int MAXV = TRIPS_MAX_VIEWS;
 constexpr int MAXL = TRIPS_MAX_LAYERS;
 constexpr uint64_t KEY_NONE = ~0ull;
+// A tile with at most FINE_E entries ("fine" tile, typical of the finest layers) is rendered
+// by one workgroup with one entry per thread: its lists are sorted in LDS, and the kept slot
+// of every corner is stored in the entry for the backward pass.
+constexpr uint32_t FINE_E = 256;
+constexpr uint32_t FINE_PER_WG = 1;  // fine tiles handled one after another by a workgroup
+// Work items are ordered by size class, largest first: class q holds items of more than
+// (NBUCKET - 1 - q) / NBUCKET of item_e entries.  info[INFO_BUCKET + q] is the first work
+// slot of class q, info[INFO_BUCKET + NBUCKET + q] its fill counter.
+constexpr int NBUCKET = 8;
+constexpr int INFO_BUCKET = 8;
+__device__ __forceinline__ uint32_t size_class(uint32_t entries, uint32_t item_e) {
+  const uint32_t short_by = item_e - min(entries, item_e);  // 0 for a full item
+  return min(uint32_t(NBUCKET - 1), uint32_t((uint64_t(short_by) * NBUCKET) / item_e));
+}
 
 struct ViewP {
   float R[9], t[3];
@@ -224,6 +238,32 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* ws, ui
   return off + inc - x;
 }
 
+// The same for four independent counters at once; `ws` holds NW uint4 of LDS.
+template <int NW>
+__device__ __forceinline__ uint4 block_excl_scan4(uint4 x, uint4* ws, uint4& total) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint4 inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t a = __shfl_up(inc.x, d, 64), b = __shfl_up(inc.y, d, 64);
+    const uint32_t c = __shfl_up(inc.z, d, 64), e = __shfl_up(inc.w, d, 64);
+    if (lane >= d) { inc.x += a; inc.y += b; inc.z += c; inc.w += e; }
+  }
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  uint4 off = make_uint4(0u, 0u, 0u, 0u), tot = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint4 s = ws[k];
+    if (k < w) { off.x += s.x; off.y += s.y; off.z += s.z; off.w += s.w; }
+    tot.x += s.x; tot.y += s.y; tot.z += s.z; tot.w += s.w;
+  }
+  __syncthreads();
+  total = tot;
+  return make_uint4(off.x + inc.x - x.x, off.y + inc.y - x.y, off.z + inc.z - x.z,
+                    off.w + inc.w - x.w);
+}
+
 // ------------------------------------------------------------------------------------
 // Per-texel top-16 in registers: keys ascending; insertion is a fixed compare network.
 
@@ -354,25 +394,52 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
                                                   uint32_t* __restrict__ bin_start,
                                                   uint32_t* __restrict__ item_start,
                                                   uint32_t* __restrict__ multi_bins,
+                                                  uint4* __restrict__ fine_work,
                                                   uint32_t* __restrict__ info, uint32_t NB,
                                                   uint32_t item_e) {
-  __shared__ uint32_t ws[16];
-  uint32_t carry_e = 0, carry_i = 0, carry_m = 0;
+  __shared__ uint4 ws[16];
+  __shared__ uint32_t s_bucket[NBUCKET];
+  if (threadIdx.x < NBUCKET) s_bucket[threadIdx.x] = 0;
+  uint32_t nb_own[NBUCKET];  // items of this thread's bins per size class
+#pragma unroll
+  for (int q = 0; q < NBUCKET; ++q) nb_own[q] = 0;
+  uint32_t carry_e = 0, carry_i = 0, carry_m = 0, carry_f = 0;
+  uint32_t nxt[4];  // the next chunk's counts, loaded one chunk ahead
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t idx = threadIdx.x * 4 + k;
+    nxt[k] = idx < NB ? tot[idx] : 0u;
+  }
   for (uint32_t base = 0; base < NB; base += 4096) {
-    uint32_t e[4], it[4], se = 0, si = 0, sm = 0;
+    // fine tiles get no work item (they are listed in fine_work); the others get one item
+    // per item_e entries
+    uint32_t e[4], it[4], se = 0, si = 0, sm = 0, sf = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      e[k] = nxt[k];
+      const uint32_t nidx = base + 4096 + threadIdx.x * 4 + k;
+      nxt[k] = nidx < NB ? tot[nidx] : 0u;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       uint32_t idx = base + threadIdx.x * 4 + k;
-      e[k] = idx < NB ? tot[idx] : 0u;
-      it[k] = idx < NB ? max(1u, (e[k] + item_e - 1) / item_e) : 0u;
+      const bool fine = idx < NB && e[k] <= FINE_E;
+      it[k] = (idx < NB && !fine) ? (e[k] + item_e - 1) / item_e : 0u;
       se += e[k];
       si += it[k];
       sm += it[k] > 1 ? 1u : 0u;
+      sf += fine ? 1u : 0u;
+      if (it[k] > 0) {  // it - 1 items of item_e entries and a last one of the rest
+        const uint32_t last = e[k] - (it[k] - 1) * item_e;
+#pragma unroll
+        for (int q = 0; q < NBUCKET; ++q)
+          nb_own[q] += (q == 0 ? it[k] - 1 : 0u) + (q == size_class(last, item_e) ? 1u : 0u);
+      }
     }
-    uint32_t te, ti, tm;
-    uint32_t oe = block_excl_scan<16>(se, ws, te);
-    uint32_t oi = block_excl_scan<16>(si, ws, ti);
-    uint32_t om = block_excl_scan<16>(sm, ws, tm);
+    uint4 t4;
+    const uint4 o4 = block_excl_scan4<16>(make_uint4(se, si, sm, sf), ws, t4);
+    uint32_t oe = o4.x, oi = o4.y, om = o4.z, of = o4.w;
+    const uint32_t te = t4.x, ti = t4.y, tm = t4.z, tf = t4.w;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       uint32_t idx = base + threadIdx.x * 4 + k;
@@ -380,15 +447,25 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
         bin_start[idx] = carry_e + oe;
         item_start[idx] = carry_i + oi;
         if (it[k] > 1) multi_bins[carry_m + om] = idx;
+        if (e[k] <= FINE_E)
+          fine_work[carry_f + of] = make_uint4(idx, carry_e + oe, carry_e + oe + e[k], 0u);
       }
       oe += e[k];
       oi += it[k];
       om += it[k] > 1 ? 1u : 0u;
+      of += (idx < NB && e[k] <= FINE_E) ? 1u : 0u;
     }
     carry_e += te;
     carry_i += ti;
     carry_m += tm;
+    carry_f += tf;
   }
+#pragma unroll
+  for (int q = 0; q < NBUCKET; ++q) {
+    const uint32_t w = wave_incl_scan(nb_own[q]);
+    if ((threadIdx.x & 63) == 63 && w) atomicAdd(&s_bucket[q], w);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     bin_start[NB] = carry_e;
     item_start[NB] = carry_i;
@@ -396,6 +473,13 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
     info[1] = carry_i;
     info[2] = 0;  // visible (point, view) pairs, accumulated by the scatter pass
     info[3] = carry_m;
+    info[4] = carry_f;
+    uint32_t o = 0;
+    for (int q = 0; q < NBUCKET; ++q) {  // first work slot of each size class; fill counters
+      info[INFO_BUCKET + q] = o;
+      info[INFO_BUCKET + NBUCKET + q] = 0;
+      o += s_bucket[q];
+    }
   }
 }
 
@@ -547,23 +631,43 @@ constexpr int EPT = 2;                // entries per thread per LDS round
 constexpr int SUB_E = EPT * TP;       // entries per LDS round
 constexpr int SUB_F = 4 * SUB_E;      // fragments per LDS round (at most 4 per entry)
 
-// item_bins: the work table in processing order (coarse layers, which hold the long lists,
-// come last in bin order and are processed first): slot w = total - 1 - it describes item it
-// as {bin, first entry, end entry, it | (bin has several items) << 31}.
+// item_bins: the work table in processing order, largest items first (size classes of
+// item_e / NBUCKET entries; the order within a class is whatever the atomics give, which
+// changes no result: every item writes its own outputs).  A slot describes item it as
+// {bin, first entry, end entry, it | (bin has several items) << 31}.  Slots are reserved per
+// workgroup and class: LDS counters, then one global atomic per class.
 __global__ __launch_bounds__(256) void k_item_bins(const uint32_t* __restrict__ item_start,
                                                    const uint32_t* __restrict__ bin_start,
+                                                   uint32_t* __restrict__ info,
                                                    uint4* __restrict__ work, uint32_t NB,
                                                    uint32_t item_e) {
+  __shared__ uint32_t s_cnt[NBUCKET], s_base[NBUCKET];
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= NB) return;
-  const uint32_t total = item_start[NB];
-  const uint32_t i0 = item_start[b], i1 = item_start[b + 1];
-  const uint32_t e_end = bin_start[b + 1];
-  const uint32_t multi = (i1 - i0 > 1) ? 0x80000000u : 0u;
-  for (uint32_t it = i0; it < i1; ++it) {
-    const uint32_t e0 = bin_start[b] + (it - i0) * item_e;
-    work[total - 1 - it] = make_uint4(b, e0, min(e0 + item_e, e_end), it | multi);
+  if (threadIdx.x < NBUCKET) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t i0 = 0, i1 = 0, e_beg = 0, e_end = 0;
+  if (b < NB) {
+    i0 = item_start[b]; i1 = item_start[b + 1];
+    e_beg = bin_start[b]; e_end = bin_start[b + 1];
   }
+  // all items but the last hold item_e entries (class 0)
+  const uint32_t nfull = i1 > i0 ? i1 - i0 - 1 : 0u;
+  const uint32_t elast = e_beg + nfull * item_e;
+  const uint32_t q = size_class(e_end - elast, item_e);
+  const uint32_t rf = nfull ? atomicAdd(&s_cnt[0], nfull) : 0u;
+  const uint32_t rl = i1 > i0 ? atomicAdd(&s_cnt[q], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x < NBUCKET && s_cnt[threadIdx.x])
+    s_base[threadIdx.x] = info[INFO_BUCKET + threadIdx.x] +
+                          atomicAdd(&info[INFO_BUCKET + NBUCKET + threadIdx.x], s_cnt[threadIdx.x]);
+  __syncthreads();
+  if (i1 == i0) return;
+  const uint32_t multi = (i1 - i0 > 1) ? 0x80000000u : 0u;
+  for (uint32_t k = 0; k < nfull; ++k) {
+    const uint32_t e0 = e_beg + k * item_e;
+    work[s_base[0] + rf + k] = make_uint4(b, e0, e0 + item_e, (i0 + k) | multi);
+  }
+  work[s_base[q] + rl] = make_uint4(b, elast, e_end, (i1 - 1) | multi);
 }
 
 // fwd_items: one workgroup per work item (coarse layers first).  Each LDS round expands
@@ -679,6 +783,162 @@ __global__ __launch_bounds__(256) void k_fwd_items(
                              uint32_t(kk[m + 1] >> 32));
 #pragma unroll
     for (int m = 0; m < KEEP; m += 4) pg[m / 4] = make_float4(kg[m], kg[m + 1], kg[m + 2], kg[m + 3]);
+  }
+}
+
+// Entry.slot of an entry of a fine tile, once the forward pass ran: bits 0..2 are the row
+// slot, bits 8 + 5c .. 12 + 5c the kept slot (0..15) of corner c, 31 if absent or not kept.
+constexpr uint32_t KSLOT_SHIFT = 8;
+constexpr uint32_t KSLOT_NONE = 31;
+
+// fwd_fine: a workgroup renders FINE_PER_WG fine tiles one after another (the next tile's
+// entries load while the current one blends), one entry per thread.  Fragments are counting-sorted
+// by texel in LDS; every fragment then counts the smaller keys of its texel's run (its
+// depth rank, computed by the threads in parallel whatever the run lengths), the first 16
+// ranks are the kept list, and the thread owning a texel blends it (Eq. 6-7) and writes
+// the same outputs as the item path.  Every entry then records the kept slot of each of its
+// corners.
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_fine(
+    const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
+    Entry* __restrict__ ent, const float* __restrict__ desc, float* __restrict__ pyr,
+    uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
+  constexpr int NF = 4 * FINE_E;     // fragment capacity
+  __shared__ uint32_t hist[TP];      // fragments per texel, then the start of its run
+  __shared__ uint32_t ws[4];
+  __shared__ uint64_t skey[NF];
+  __shared__ float sgam[NF];
+  __shared__ uint16_t sord[NF];      // at run start + m: run position of the m-th kept fragment
+  __shared__ uint8_t sslot[NF];      // kept slot (depth rank) of each fragment, 0xff if not kept
+  __shared__ uint8_t stex[NF];       // texel of each fragment
+  static_assert(FINE_E == TP, "one entry per thread");
+  const int t = threadIdx.x;
+  const uint32_t nf = info[4];
+  const uint32_t f0 = blockIdx.x * FINE_PER_WG;
+  if (f0 >= nf) return;
+  const uint32_t f1 = min(f0 + FINE_PER_WG, nf);
+  uint4 wk = fine_work[f0];
+  bool has = wk.y + uint32_t(t) < wk.z;
+  Entry en = {};
+  if (has) en = ent[wk.y + t];
+  for (uint32_t f = f0; f < f1; ++f) {
+    const uint4 wn = f + 1 < f1 ? fine_work[f + 1] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t b = wk.x, e0 = wk.y;
+    const BinInfo bi = decode_bin(P, b);
+    hist[t] = 0;
+    __syncthreads();
+    Corner cs[4];
+    uint32_t cm = 0, rank[4] = {0u, 0u, 0u, 0u};
+    if (has) cm = entry_corners(en, bi, P.ltw, cs);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if ((cm >> c) & 1u) rank[c] = atomicAdd(&hist[cs[c].p], 1u);
+    __syncthreads();
+    const uint32_t cnt = hist[t];
+    uint32_t tot;
+    const uint32_t base = block_excl_scan<4>(cnt, ws, tot);
+    hist[t] = base;  // all counts were read before the scan's first barrier
+    __syncthreads();
+    const uint64_t key = (uint64_t(en.zbits) << 32) | en.idx;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if ((cm >> c) & 1u) {
+        const uint32_t o = hist[cs[c].p] + rank[c];
+        skey[o] = key;
+        sgam[o] = (cs[c].wx * cs[c].wy) * en.ia;
+        stex[o] = uint8_t(cs[c].p);
+      }
+    __syncthreads();
+    // depth rank of every fragment within its texel (keys are distinct within a texel)
+    for (uint32_t o = t; o < tot; o += TP) {
+      const uint32_t p = stex[o];
+      const uint32_t r0 = hist[p], r1 = p + 1 < TP ? hist[p + 1] : tot;
+      const uint64_t ko = skey[o];
+      uint32_t rk = 0;
+      for (uint32_t r = r0; r < r1; r += 4) {
+        uint64_t kq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) kq[q] = r + q < r1 ? skey[r + q] : KEY_NONE;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rk += kq[q] < ko ? 1u : 0u;
+      }
+      sslot[o] = rk < KEEP ? uint8_t(rk) : uint8_t(0xff);
+      if (rk < KEEP) sord[r0 + rk] = uint16_t(o - r0);
+    }
+    __syncthreads();
+    // the next tile's entries are loaded while this one is blended
+    const bool has_n = wn.y + uint32_t(t) < wn.z;
+    Entry enn = {};
+    if (has_n) enn = ent[wn.y + t];
+    if (has) {  // the kept slot of every corner, for the backward pass
+      uint32_t packed = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        uint32_t m = KSLOT_NONE;
+        if ((cm >> c) & 1u) {
+          const uint32_t s8 = sslot[hist[cs[c].p] + rank[c]];
+          m = s8 < KEEP ? s8 : KSLOT_NONE;
+        }
+        packed |= m << (5 * c);
+      }
+      ent[e0 + t].slot = (en.slot & 7u) | (packed << KSLOT_SHIFT);
+    }
+    // blend, with the descriptor gathers of GB fragments issued before they are used
+    const uint32_t k = min(cnt, uint32_t(KEEP));
+    {
+      const int lth = 8 - P.ltw;
+      const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+      const int j = (bi.ty << lth) + (t >> P.ltw);
+      float C[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) C[d] = 0.0f;
+      float T = 1.0f;
+      constexpr int GB = D > 4 ? 2 : 4;  // fine tiles keep few fragments per texel
+      for (uint32_t m0 = 0; m0 < k; m0 += GB) {
+        float4 tv[GB][D / 4];
+        uint64_t kq[GB];
+        float gq[GB];
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+          const uint32_t m = m0 + q;
+          const bool v = m < k;
+          const uint32_t r = v ? sord[base + m] : 0u;
+          kq[q] = v ? skey[base + r] : KEY_NONE;
+          gq[q] = v ? sgam[base + r] : 0.0f;
+          const float4* tp = reinterpret_cast<const float4*>(desc + size_t(uint32_t(kq[q])) * D);
+#pragma unroll
+          for (int r4 = 0; r4 < D / 4; ++r4) tv[q][r4] = v ? tp[r4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+          const uint32_t m = m0 + q;
+          if (m < k) {
+            const float w = T * gq[q];
+#pragma unroll
+            for (int r4 = 0; r4 < D / 4; ++r4) {
+              C[4 * r4 + 0] += w * tv[q][r4].x;
+              C[4 * r4 + 1] += w * tv[q][r4].y;
+              C[4 * r4 + 2] += w * tv[q][r4].z;
+              C[4 * r4 + 3] += w * tv[q][r4].w;
+            }
+            T = T * (1.0f - gq[q]);
+            kkey[(size_t(b) * KEEP + m) * TP + t] = kq[q];
+            kgam[(size_t(b) * KEEP + m) * TP + t] = gq[q];
+          }
+        }
+      }
+      if (i < bi.WL && j < bi.HL) {
+        const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+        float4* op = reinterpret_cast<float4*>(pyr + o);
+#pragma unroll
+        for (int q = 0; q < D / 4; ++q) op[q] = make_float4(C[4 * q], C[4 * q + 1], C[4 * q + 2], C[4 * q + 3]);
+      }
+      npix[size_t(b) * TP + t] = cnt;
+    }
+    wk = wn;
+    has = has_n;
+    en = enn;
+    __syncthreads();  // LDS is reused by the next tile
   }
 }
 
@@ -891,6 +1151,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     const uint32_t* __restrict__ npix, const uint64_t* __restrict__ kkey,
     const float2* __restrict__ bst, const float* __restrict__ gpyr, float* __restrict__ rows) {
   constexpr int RW = 4 + D;
+  constexpr int EB = 2;  // entries per thread in flight
   __shared__ uint32_t s_k[TP];
   __shared__ uint64_t s_last[TP];
   __shared__ uint4 s_idx[TP][KEEP / 4];  // kept point ids of each texel, contiguous
@@ -900,6 +1161,11 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   const uint4 wk = work[blockIdx.x];
   if (blockIdx.x >= total) return;
   const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z;
+  // the first entries of this thread, loaded while the tile is staged
+  Entry nx[EB];
+#pragma unroll
+  for (int q = 0; q < EB; ++q)
+    if (e0 + q * TP + t < e1) nx[q] = ent[e0 + q * TP + t];
   const BinInfo bi = decode_bin(P, b);
   const int lth = 8 - P.ltw;
   {  // stage the tile's kept point ids, last kept keys and upstream gradient
@@ -926,59 +1192,155 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     }
   }
   __syncthreads();
-  Entry nxt;
-  if (e0 + t < e1) nxt = ent[e0 + t];
-  for (uint32_t e = e0 + t; e < e1; e += TP) {
-    const Entry en = nxt;
-    if (e + TP < e1) nxt = ent[e + TP];  // prefetch the next entry of this thread
-    Corner cs[4];
-    uint32_t cm = entry_corners(en, bi, P.ltw, cs);
-    const uint64_t key = (uint64_t(en.zbits) << 32) | en.idx;
-    size_t pos[4];
+  for (uint32_t e = e0 + t; e < e1; e += EB * TP) {
+    Entry en[EB];
+    bool valid[EB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      pos[q] = 0;
-      if (!((cm >> q) & 1u)) continue;
-      const int p = cs[q].p;
-      const uint32_t kp = s_k[p];
-      uint32_t m = kp;
-      if (kp != 0 && !(key > s_last[p])) {  // among the kept fragments: find its position
+    for (int q = 0; q < EB; ++q) {
+      en[q] = nx[q];
+      valid[q] = e + q * TP < e1;
+      if (e + (EB + q) * TP < e1) nx[q] = ent[e + (EB + q) * TP];  // next round of entries
+    }
+    // find the kept slot of every corner, then gather the blend adjoints of all of them
+    Corner cs[EB][4];
+    uint32_t cm[EB];
+    size_t pos[EB][4];
 #pragma unroll
-        for (int j = 0; j < KEEP / 4; ++j) {
-          const uint4 v = s_idx[p][j];
-          m = (v.x == en.idx && uint32_t(4 * j) < kp) ? uint32_t(4 * j) : m;
-          m = (v.y == en.idx && uint32_t(4 * j + 1) < kp) ? uint32_t(4 * j + 1) : m;
-          m = (v.z == en.idx && uint32_t(4 * j + 2) < kp) ? uint32_t(4 * j + 2) : m;
-          m = (v.w == en.idx && uint32_t(4 * j + 3) < kp) ? uint32_t(4 * j + 3) : m;
+    for (int h = 0; h < EB; ++h) {
+      cm[h] = valid[h] ? entry_corners(en[h], bi, P.ltw, cs[h]) : 0u;
+      const uint64_t key = (uint64_t(en[h].zbits) << 32) | en[h].idx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pos[h][q] = 0;
+        if (!((cm[h] >> q) & 1u)) continue;
+        const int p = cs[h][q].p;
+        const uint32_t kp = s_k[p];
+        uint32_t m = kp;
+        if (kp != 0 && !(key > s_last[p])) {  // among the kept fragments: find its position
+#pragma unroll
+          for (int j = 0; j < KEEP / 4; ++j) {
+            const uint4 v = s_idx[p][j];
+            m = (v.x == en[h].idx && uint32_t(4 * j) < kp) ? uint32_t(4 * j) : m;
+            m = (v.y == en[h].idx && uint32_t(4 * j + 1) < kp) ? uint32_t(4 * j + 1) : m;
+            m = (v.z == en[h].idx && uint32_t(4 * j + 2) < kp) ? uint32_t(4 * j + 2) : m;
+            m = (v.w == en[h].idx && uint32_t(4 * j + 3) < kp) ? uint32_t(4 * j + 3) : m;
+          }
         }
+        if (m == kp) cm[h] &= ~(1u << q);
+        else pos[h][q] = (size_t(b) * KEEP + m) * TP + uint32_t(p);
       }
-      if (m == kp) cm &= ~(1u << q);
-      else pos[q] = (size_t(b) * KEEP + m) * TP + uint32_t(p);
     }
-    float2 st[4];
+    float2 st[EB][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) st[q] = ((cm >> q) & 1u) ? bst[pos[q]] : make_float2(0.f, 0.f);
-    float A = 0.0f, Bx = 0.0f, By = 0.0f;
-    float tau[D];
+    for (int h = 0; h < EB; ++h)
 #pragma unroll
-    for (int d = 0; d < D; ++d) tau[d] = 0.0f;
+      for (int q = 0; q < 4; ++q)
+        st[h][q] = ((cm[h] >> q) & 1u) ? bst[pos[h][q]] : make_float2(0.f, 0.f);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((cm >> q) & 1u)) continue;
-      const int p = cs[q].p;
-      const float dg = st[q].x;
-      A += dg * (cs[q].wx * cs[q].wy);
-      Bx += dg * (cs[q].sx * cs[q].wy);
-      By += dg * (cs[q].wx * cs[q].sy);
+    for (int h = 0; h < EB; ++h) {
+      if (!valid[h]) continue;
+      float A = 0.0f, Bx = 0.0f, By = 0.0f;
+      float tau[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) tau[d] += st[q].y * s_G[p][d];
+      for (int d = 0; d < D; ++d) tau[d] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!((cm[h] >> q) & 1u)) continue;
+        const int p = cs[h][q].p;
+        const float dg = st[h][q].x;
+        A += dg * (cs[h][q].wx * cs[h][q].wy);
+        Bx += dg * (cs[h][q].sx * cs[h][q].wy);
+        By += dg * (cs[h][q].wx * cs[h][q].sy);
+#pragma unroll
+        for (int d = 0; d < D; ++d) tau[d] += st[h][q].y * s_G[p][d];
+      }
+      float* r = rows + ((size_t(bi.v) * NSLOT + (en[h].slot & 7u)) * size_t(P.n) + en[h].idx) * RW;
+      float4* r4 = reinterpret_cast<float4*>(r);
+      r4[0] = make_float4(A, Bx, By, 0.0f);
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q)
+        r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
     }
-    float* r = rows + ((size_t(bi.v) * NSLOT + en.slot) * size_t(P.n) + en.idx) * RW;
-    float4* r4 = reinterpret_cast<float4*>(r);
-    r4[0] = make_float4(A, Bx, By, 0.0f);
+  }
+}
+
+// bwd_fine: the entry rows of FINE_PER_WG fine tiles per workgroup, one entry per thread.
+// The kept slot of every corner was recorded by the forward pass, so no kept list is searched.
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_fine(
+    const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
+    const Entry* __restrict__ ent, const float2* __restrict__ bst, const float* __restrict__ gpyr,
+    float* __restrict__ rows) {
+  constexpr int RW = 4 + D;
+  __shared__ float s_G[TP][D + 1];
+  const int t = threadIdx.x;
+  const uint32_t nf = info[4];
+  const uint32_t f0 = blockIdx.x * FINE_PER_WG;
+  if (f0 >= nf) return;
+  const uint32_t f1 = min(f0 + FINE_PER_WG, nf);
+  uint4 wk = fine_work[f0];
+  bool has = wk.y + uint32_t(t) < wk.z;
+  Entry en = {};
+  if (has) en = ent[wk.y + t];
+  for (uint32_t f = f0; f < f1; ++f) {
+    const uint4 wn = f + 1 < f1 ? fine_work[f + 1] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t b = wk.x;
+    const BinInfo bi = decode_bin(P, b);
+    {  // upstream gradient of the tile's texels inside the layer
+      const int lth = 8 - P.ltw;
+      const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+      const int j = (bi.ty << lth) + (t >> P.ltw);
+      if (i < bi.WL && j < bi.HL) {
+        const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
 #pragma unroll
-    for (int q = 0; q < D / 4; ++q)
-      r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
+        for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
+      }
+    }
+    __syncthreads();
+    const bool has_n = wn.y + uint32_t(t) < wn.z;
+    Entry enn = {};
+    if (has_n) enn = ent[wn.y + t];
+    if (has) {
+      Corner cs[4];
+      uint32_t cm = entry_corners(en, bi, P.ltw, cs);
+      const uint32_t packed = en.slot >> KSLOT_SHIFT;
+      size_t pos[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t m = (packed >> (5 * q)) & 31u;
+        pos[q] = 0;
+        if (((cm >> q) & 1u) && m < KEEP) pos[q] = (size_t(b) * KEEP + m) * TP + uint32_t(cs[q].p);
+        else cm &= ~(1u << q);
+      }
+      float2 st[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) st[q] = ((cm >> q) & 1u) ? bst[pos[q]] : make_float2(0.f, 0.f);
+      float A = 0.0f, Bx = 0.0f, By = 0.0f;
+      float tau[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) tau[d] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!((cm >> q) & 1u)) continue;
+        const int p = cs[q].p;
+        const float dg = st[q].x;
+        A += dg * (cs[q].wx * cs[q].wy);
+        Bx += dg * (cs[q].sx * cs[q].wy);
+        By += dg * (cs[q].wx * cs[q].sy);
+#pragma unroll
+        for (int d = 0; d < D; ++d) tau[d] += st[q].y * s_G[p][d];
+      }
+      float* r = rows + ((size_t(bi.v) * NSLOT + (en.slot & 7u)) * size_t(P.n) + en.idx) * RW;
+      float4* r4 = reinterpret_cast<float4*>(r);
+      r4[0] = make_float4(A, Bx, By, 0.0f);
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q)
+        r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
+    }
+    wk = wn;
+    has = has_n;
+    en = enn;
+    __syncthreads();  // s_G is reused by the next tile
   }
 }
 
@@ -1066,10 +1428,11 @@ thread_local int32_t g_last_hip = 0;
 // Optional per-kernel timing (reports only): a start and an end event around every kernel
 // launch, on the launch stream; read back and summed per stage by trips_timing_read.
 enum Stage { ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_ITEM_BINS, ST_SCATTER, ST_FWD_ITEMS,
-             ST_FWD_MERGE, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_POINTS, ST_EXPORT, NUM_STAGES };
+             ST_FWD_FINE, ST_FWD_MERGE, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_FINE, ST_BWD_POINTS,
+             ST_EXPORT, NUM_STAGES };
 const char* const kStageNames[NUM_STAGES] = {
-    "count", "colscan", "binscan", "item_bins", "scatter", "fwd_items", "fwd_merge",
-    "bwd_pixels", "bwd_items", "bwd_points", "export"};
+    "count", "colscan", "binscan", "item_bins", "scatter", "fwd_items", "fwd_fine", "fwd_merge",
+    "bwd_pixels", "bwd_items", "bwd_fine", "bwd_points", "export"};
 static_assert(NUM_STAGES == TRIPS_NUM_STAGES, "stage table");
 
 struct TimingState {
@@ -1114,7 +1477,8 @@ struct Layout {
   uint64_t icap;      // work-item capacity
   uint64_t npyr;      // texels of all views and layers
   // saved buffer
-  size_t s_info, s_bin_start, s_item_start, s_multi, s_npix, s_kkey, s_kgam, s_tables_end, s_work, s_ent;
+  size_t s_info, s_bin_start, s_item_start, s_multi, s_fine, s_npix, s_kkey, s_kgam, s_tables_end,
+      s_work, s_ent;
   size_t saved_bytes;
   // workspace
   size_t w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, ws_bytes;
@@ -1138,7 +1502,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   if (cfg->desc_dim < 1 || cfg->max_list < 1) return TRIPS_ERR_INVALID_ARG;
   if (cfg->max_list != KEEP) return TRIPS_ERR_UNSUPPORTED;
   if (cfg->desc_dim != 4 && cfg->desc_dim != 8) return TRIPS_ERR_UNSUPPORTED;
-  int tile_w = 16, pb = 4096, item_e = 4096;
+  int tile_w = 16, pb = 4096, item_e = 8192;
   if (tun) {
     if (tun->tile_w) tile_w = tun->tile_w;
     if (tun->points_per_block) pb = tun->points_per_block;
@@ -1202,6 +1566,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.s_bin_start = take((NB + 1) * 4);
   lay.s_item_start = take((NB + 1) * 4);
   lay.s_multi = take(NB * 4);
+  lay.s_fine = take(NB * sizeof(uint4));
   // texel tables: their offsets depend only on the cameras and config (export reads them)
   lay.s_npix = take(NB * TP * 4);
   lay.s_kkey = take(NB * TP * KEEP * 8);
@@ -1260,6 +1625,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   uint32_t* item_start = reinterpret_cast<uint32_t*>(sv + lay.s_item_start);
   uint4* work = reinterpret_cast<uint4*>(sv + lay.s_work);
   uint32_t* multi_bins = reinterpret_cast<uint32_t*>(sv + lay.s_multi);
+  uint4* fine_work = reinterpret_cast<uint4*>(sv + lay.s_fine);
   uint32_t* npix = reinterpret_cast<uint32_t*>(sv + lay.s_npix);
   uint64_t* kkey = reinterpret_cast<uint64_t*>(sv + lay.s_kkey);
   float* kgam = reinterpret_cast<float*>(sv + lay.s_kgam);
@@ -1283,13 +1649,13 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   {
     StageTimer tm(ST_BINSCAN, st);
     hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, tot, bin_start, item_start,
-                       multi_bins, info, P.NB, P.item_e);
+                       multi_bins, fine_work, info, P.NB, P.item_e);
   }
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_ITEM_BINS, st);
     hipLaunchKernelGGL(k_item_bins, dim3((P.NB + 255) / 256), dim3(256), 0, st, item_start,
-                       bin_start, work, P.NB, P.item_e);
+                       bin_start, info, work, P.NB, P.item_e);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.nblk > 0) {
@@ -1310,6 +1676,13 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
                        ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam);
   }
   TRIPS_HIP(hipGetLastError());
+  {  // one workgroup per fine tile; workgroups beyond their count exit at once
+    StageTimer tm(ST_FWD_FINE, st);
+    hipLaunchKernelGGL(k_fwd_fine<D>, dim3((P.NB + FINE_PER_WG - 1) / FINE_PER_WG), dim3(256), 0,
+                       st, P, info, fine_work, ent,
+                       pts.desc, pyr, npix, kkey, kgam);
+  }
+  TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_FWD_MERGE, st);
     hipLaunchKernelGGL(k_fwd_merge<D>, dim3(1024), dim3(256), 0, st, P, item_start, multi_bins,
@@ -1328,6 +1701,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   float* rows = reinterpret_cast<float*>(ws + lay.w_rows);
   const uint32_t* info = reinterpret_cast<const uint32_t*>(sv + lay.s_info);
   const uint4* work = reinterpret_cast<const uint4*>(sv + lay.s_work);
+  const uint4* fine_work = reinterpret_cast<const uint4*>(sv + lay.s_fine);
   const uint32_t* npix = reinterpret_cast<const uint32_t*>(sv + lay.s_npix);
   const uint64_t* kkey = reinterpret_cast<const uint64_t*>(sv + lay.s_kkey);
   const float* kgam = reinterpret_cast<const float*>(sv + lay.s_kgam);
@@ -1343,6 +1717,12 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     StageTimer tm(ST_BWD_ITEMS, st);
     hipLaunchKernelGGL(k_bwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info, work,
                        ent, npix, kkey, bst, gpyr, rows);
+  }
+  TRIPS_HIP(hipGetLastError());
+  {
+    StageTimer tm(ST_BWD_FINE, st);
+    hipLaunchKernelGGL(k_bwd_fine<D>, dim3((P.NB + FINE_PER_WG - 1) / FINE_PER_WG), dim3(256), 0,
+                       st, P, info, fine_work, ent, bst, gpyr, rows);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.n > 0) {
@@ -1512,14 +1892,37 @@ trips_status trips_forward_stats(const trips_config* cfg, const trips_camera* ca
   if (s != TRIPS_OK) return s;
   if (!saved || !aligned(saved) || !stats) return TRIPS_ERR_INVALID_ARG;
   if (saved_bytes < lay.s_bin_start) return TRIPS_ERR_WORKSPACE;
-  uint32_t info[3] = {0, 0, 0};
+  uint32_t info[5] = {0, 0, 0, 0, 0};
   TRIPS_HIP(hipMemcpyAsync(info, static_cast<const char*>(saved) + lay.s_info, sizeof(info),
                            hipMemcpyDeviceToHost, st));
   TRIPS_HIP(hipStreamSynchronize(st));
   stats[0] = info[0];
-  stats[1] = info[1];
+  stats[1] = int64_t(info[1]) + info[4];  // item workgroups + fine-tile workgroups
   stats[2] = lay.P.NB;
   stats[3] = info[2];
+  return TRIPS_OK;
+}
+
+trips_status trips_tile_stats(const trips_config* cfg, const trips_camera* cams, int32_t views,
+                              const trips_tuning* tun, const void* saved, size_t saved_bytes,
+                              uint32_t* entries, uint32_t* kept, hipStream_t st) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, 0, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if (!saved || !aligned(saved) || !entries || !kept) return TRIPS_ERR_INVALID_ARG;
+  if (saved_bytes < lay.s_tables_end) return TRIPS_ERR_WORKSPACE;
+  const size_t NB = lay.P.NB;
+  std::vector<uint32_t> bs(NB + 1), np(NB * TP);
+  const char* sv = static_cast<const char*>(saved);
+  TRIPS_HIP(hipMemcpyAsync(bs.data(), sv + lay.s_bin_start, (NB + 1) * 4, hipMemcpyDeviceToHost, st));
+  TRIPS_HIP(hipMemcpyAsync(np.data(), sv + lay.s_npix, NB * TP * 4, hipMemcpyDeviceToHost, st));
+  TRIPS_HIP(hipStreamSynchronize(st));
+  for (size_t b = 0; b < NB; ++b) {
+    entries[b] = bs[b + 1] - bs[b];
+    uint32_t k = 0;
+    for (int t = 0; t < TP; ++t) k += std::min<uint32_t>(np[b * TP + t], KEEP);
+    kept[b] = k;
+  }
   return TRIPS_OK;
 }
 
