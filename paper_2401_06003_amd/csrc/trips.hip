@@ -47,7 +47,6 @@ constexpr uint64_t KEY_NONE = ~0ull;
 // by one workgroup with one entry per thread: its lists are sorted in LDS, and the kept slot
 // of every corner is stored in the entry for the backward pass.
 constexpr uint32_t FINE_E = 256;
-constexpr uint32_t FINE_PER_WG = 1;  // fine tiles handled one after another by a workgroup
 // Work items are ordered by size class, largest first: class q holds items of more than
 // (NBUCKET - 1 - q) / NBUCKET of item_e entries.  info[INFO_BUCKET + q] is the first work
 // slot of class q, info[INFO_BUCKET + NBUCKET + q] its fill counter.
@@ -395,6 +394,7 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
                                                   uint32_t* __restrict__ item_start,
                                                   uint32_t* __restrict__ multi_bins,
                                                   uint4* __restrict__ fine_work,
+                                                  uint32_t* __restrict__ coarse_bins,
                                                   uint32_t* __restrict__ info, uint32_t NB,
                                                   uint32_t item_e) {
   __shared__ uint4 ws[16];
@@ -449,6 +449,8 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
         if (it[k] > 1) multi_bins[carry_m + om] = idx;
         if (e[k] <= FINE_E)
           fine_work[carry_f + of] = make_uint4(idx, carry_e + oe, carry_e + oe + e[k], 0u);
+        else
+          coarse_bins[idx - (carry_f + of)] = idx;  // tiles before idx that are not fine
       }
       oe += e[k];
       oi += it[k];
@@ -474,6 +476,7 @@ __global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ t
     info[2] = 0;  // visible (point, view) pairs, accumulated by the scatter pass
     info[3] = carry_m;
     info[4] = carry_f;
+    info[5] = NB - carry_f;
     uint32_t o = 0;
     for (int q = 0; q < NBUCKET; ++q) {  // first work slot of each size class; fill counters
       info[INFO_BUCKET + q] = o;
@@ -791,12 +794,12 @@ __global__ __launch_bounds__(256) void k_fwd_items(
 constexpr uint32_t KSLOT_SHIFT = 8;
 constexpr uint32_t KSLOT_NONE = 31;
 
-// fwd_fine: a workgroup renders FINE_PER_WG fine tiles one after another (the next tile's
-// entries load while the current one blends), one entry per thread.  Fragments are counting-sorted
+// fwd_fine: one workgroup per fine tile, one entry per thread.  Fragments are counting-sorted
 // by texel in LDS; every fragment then counts the smaller keys of its texel's run (its
 // depth rank, computed by the threads in parallel whatever the run lengths), the first 16
 // ranks are the kept list, and the thread owning a texel blends it (Eq. 6-7) and writes
-// the same outputs as the item path.  Every entry then records the kept slot of each of its
+// the same outputs as the item path.  Each entry's descriptor is loaded at the start and
+// read from LDS by the blend.  Every entry then records the kept slot of each of its
 // corners.
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_fine(
@@ -811,18 +814,26 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
   __shared__ uint16_t sord[NF];      // at run start + m: run position of the m-th kept fragment
   __shared__ uint8_t sslot[NF];      // kept slot (depth rank) of each fragment, 0xff if not kept
   __shared__ uint8_t stex[NF];       // texel of each fragment
+  __shared__ uint8_t sent[NF];       // entry (thread) of each fragment
+  __shared__ float4 sdesc[FINE_E][D / 4];  // descriptor of each entry's point
   static_assert(FINE_E == TP, "one entry per thread");
   const int t = threadIdx.x;
-  const uint32_t nf = info[4];
-  const uint32_t f0 = blockIdx.x * FINE_PER_WG;
-  if (f0 >= nf) return;
-  const uint32_t f1 = min(f0 + FINE_PER_WG, nf);
-  uint4 wk = fine_work[f0];
-  bool has = wk.y + uint32_t(t) < wk.z;
+  const uint4 wk = fine_work[blockIdx.x];  // in bounds (grid = bin count); used only if valid
+  if (blockIdx.x >= info[4]) return;
+  const bool has = wk.y + uint32_t(t) < wk.z;
   Entry en = {};
   if (has) en = ent[wk.y + t];
-  for (uint32_t f = f0; f < f1; ++f) {
-    const uint4 wn = f + 1 < f1 ? fine_work[f + 1] : make_uint4(0u, 0u, 0u, 0u);
+  {
+    // every entry's descriptor is loaded now and used after the sort (in a fine tile
+    // nearly every fragment is kept)
+    float4 dv[D / 4];
+#pragma unroll
+    for (int r4 = 0; r4 < D / 4; ++r4) dv[r4] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (has) {
+      const float4* dp = reinterpret_cast<const float4*>(desc + size_t(en.idx) * D);
+#pragma unroll
+      for (int r4 = 0; r4 < D / 4; ++r4) dv[r4] = dp[r4];
+    }
     const uint32_t b = wk.x, e0 = wk.y;
     const BinInfo bi = decode_bin(P, b);
     hist[t] = 0;
@@ -847,7 +858,10 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
         skey[o] = key;
         sgam[o] = (cs[c].wx * cs[c].wy) * en.ia;
         stex[o] = uint8_t(cs[c].p);
+        sent[o] = uint8_t(t);
       }
+#pragma unroll
+    for (int r4 = 0; r4 < D / 4; ++r4) sdesc[t][r4] = dv[r4];
     __syncthreads();
     // depth rank of every fragment within its texel (keys are distinct within a texel)
     for (uint32_t o = t; o < tot; o += TP) {
@@ -866,10 +880,6 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
       if (rk < KEEP) sord[r0 + rk] = uint16_t(o - r0);
     }
     __syncthreads();
-    // the next tile's entries are loaded while this one is blended
-    const bool has_n = wn.y + uint32_t(t) < wn.z;
-    Entry enn = {};
-    if (has_n) enn = ent[wn.y + t];
     if (has) {  // the kept slot of every corner, for the backward pass
       uint32_t packed = 0;
 #pragma unroll
@@ -883,7 +893,7 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
       }
       ent[e0 + t].slot = (en.slot & 7u) | (packed << KSLOT_SHIFT);
     }
-    // blend, with the descriptor gathers of GB fragments issued before they are used
+    // blend front to back
     const uint32_t k = min(cnt, uint32_t(KEEP));
     {
       const int lth = 8 - P.ltw;
@@ -893,39 +903,24 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
 #pragma unroll
       for (int d = 0; d < D; ++d) C[d] = 0.0f;
       float T = 1.0f;
-      constexpr int GB = D > 4 ? 2 : 4;  // fine tiles keep few fragments per texel
-      for (uint32_t m0 = 0; m0 < k; m0 += GB) {
-        float4 tv[GB][D / 4];
-        uint64_t kq[GB];
-        float gq[GB];
+#pragma unroll 1
+      for (uint32_t m = 0; m < k; ++m) {
+        const uint32_t o = base + sord[base + m];
+        const uint64_t kq = skey[o];
+        const float gq = sgam[o];
+        const uint32_t eo = sent[o];
+        const float w = T * gq;
 #pragma unroll
-        for (int q = 0; q < GB; ++q) {
-          const uint32_t m = m0 + q;
-          const bool v = m < k;
-          const uint32_t r = v ? sord[base + m] : 0u;
-          kq[q] = v ? skey[base + r] : KEY_NONE;
-          gq[q] = v ? sgam[base + r] : 0.0f;
-          const float4* tp = reinterpret_cast<const float4*>(desc + size_t(uint32_t(kq[q])) * D);
-#pragma unroll
-          for (int r4 = 0; r4 < D / 4; ++r4) tv[q][r4] = v ? tp[r4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int r4 = 0; r4 < D / 4; ++r4) {
+          const float4 tv = sdesc[eo][r4];
+          C[4 * r4 + 0] += w * tv.x;
+          C[4 * r4 + 1] += w * tv.y;
+          C[4 * r4 + 2] += w * tv.z;
+          C[4 * r4 + 3] += w * tv.w;
         }
-#pragma unroll
-        for (int q = 0; q < GB; ++q) {
-          const uint32_t m = m0 + q;
-          if (m < k) {
-            const float w = T * gq[q];
-#pragma unroll
-            for (int r4 = 0; r4 < D / 4; ++r4) {
-              C[4 * r4 + 0] += w * tv[q][r4].x;
-              C[4 * r4 + 1] += w * tv[q][r4].y;
-              C[4 * r4 + 2] += w * tv[q][r4].z;
-              C[4 * r4 + 3] += w * tv[q][r4].w;
-            }
-            T = T * (1.0f - gq[q]);
-            kkey[(size_t(b) * KEEP + m) * TP + t] = kq[q];
-            kgam[(size_t(b) * KEEP + m) * TP + t] = gq[q];
-          }
-        }
+        T = T * (1.0f - gq);
+        kkey[(size_t(b) * KEEP + m) * TP + t] = kq;
+        kgam[(size_t(b) * KEEP + m) * TP + t] = gq;
       }
       if (i < bi.WL && j < bi.HL) {
         const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
@@ -935,10 +930,6 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
       }
       npix[size_t(b) * TP + t] = cnt;
     }
-    wk = wn;
-    has = has_n;
-    en = enn;
-    __syncthreads();  // LDS is reused by the next tile
   }
 }
 
@@ -1064,18 +1055,39 @@ __global__ __launch_bounds__(256) void k_export(const Params P, const uint32_t* 
     ids[o * KEEP + m] = uint32_t(m) < n ? int32_t(uint32_t(kkey[(size_t(b) * KEEP + m) * TP + t])) : -1;
 }
 
+// g_m = G . tau_m, summed in one fixed order.
+template <int D>
+__device__ __forceinline__ float dot_g(const float (&G)[D], const float4 (&tv)[D / 4]) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int r = 0; r < D / 4; ++r)
+    acc += G[4 * r] * tv[r].x + G[4 * r + 1] * tv[r].y + G[4 * r + 2] * tv[r].z + G[4 * r + 3] * tv[r].w;
+  return acc;
+}
+
+// One step of the reverse blend recurrence for kept fragment m (B holds B_m on entry and
+// B_{m-1} on return): returns (dL/dgamma_m, T_m gamma_m).
+__device__ __forceinline__ float2 blend_adjoint_step(float Tm, float gam, float gm, float& B) {
+  const float dgam = Tm * (gm - B);
+  B = gam * gm + (1.0f - gam) * B;
+  return make_float2(dgam, Tm * gam);
+}
+
 // bwd_pixels: per texel, recompute transmittance T_m front to back and run the reverse
 // recurrence B_{m-1} = gamma_m g_m + (1 - gamma_m) B_m (g_m = G . tau_m, B_last = 0):
 // dL/dgamma_m = T_m (g_m - B_m); the descriptor gets T_m gamma_m G.
 template <int D>
-__global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32_t* __restrict__ npix,
+__global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32_t* __restrict__ info,
+                                                    const uint32_t* __restrict__ coarse_bins,
+                                                    const uint32_t* __restrict__ npix,
                                                     const uint64_t* __restrict__ kkey,
                                                     const float* __restrict__ kgam,
                                                     const float* __restrict__ desc,
                                                     const float* __restrict__ gpyr,
                                                     float2* __restrict__ bst) {
   const int t = threadIdx.x;
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = coarse_bins[blockIdx.x];  // in bounds (grid = bin count); used if valid
+  if (blockIdx.x >= info[5]) return;
   const uint32_t n = npix[size_t(b) * TP + t];
   if (n == 0) return;
   const BinInfo bi = decode_bin(P, b);
@@ -1119,24 +1131,12 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
         tv[q][r] = uint32_t(m0 + q) < k ? tp[r] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
-    for (int q = 0; q < GB; ++q) {
-      float acc = 0.0f;
-#pragma unroll
-      for (int r = 0; r < D / 4; ++r)
-        acc += G[4 * r] * tv[q][r].x + G[4 * r + 1] * tv[q][r].y + G[4 * r + 2] * tv[q][r].z +
-               G[4 * r + 3] * tv[q][r].w;
-      gm[m0 + q] = acc;
-    }
+    for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
   }
   float B = 0.0f;
 #pragma unroll
-  for (int m = KEEP - 1; m >= 0; --m) {
-    if (uint32_t(m) < k) {
-      const float dgam = Tm[m] * (gm[m] - B);
-      B = gam[m] * gm[m] + (1.0f - gam[m]) * B;
-      bst[(size_t(b) * KEEP + m) * TP + t] = make_float2(dgam, Tm[m] * gam[m]);
-    }
-  }
+  for (int m = KEEP - 1; m >= 0; --m)
+    if (uint32_t(m) < k) bst[(size_t(b) * KEEP + m) * TP + t] = blend_adjoint_step(Tm[m], gam[m], gm[m], B);
 }
 
 // bwd_items: per work item, each entry finds its corners in the tile's kept lists and writes
@@ -1264,84 +1264,118 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   }
 }
 
-// bwd_fine: the entry rows of FINE_PER_WG fine tiles per workgroup, one entry per thread.
-// The kept slot of every corner was recorded by the forward pass, so no kept list is searched.
+// bwd_fine: the backward of fine tiles, one workgroup per tile and one entry per thread.
+// The kept slot of every corner was recorded by the forward pass, so the kept lists are
+// rebuilt in LDS from the entries themselves (compact: texel t's list starts at s_off[t]);
+// each texel's thread runs the blend adjoint (as bwd_pixels does) and every entry then
+// writes its row (as bwd_items does).
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_fine(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
-    const Entry* __restrict__ ent, const float2* __restrict__ bst, const float* __restrict__ gpyr,
-    float* __restrict__ rows) {
+    const Entry* __restrict__ ent, const uint32_t* __restrict__ npix,
+    const float* __restrict__ desc, const float* __restrict__ gpyr, float* __restrict__ rows) {
   constexpr int RW = 4 + D;
+  constexpr int NF = 4 * FINE_E;  // at most one kept fragment per fragment
   __shared__ float s_G[TP][D + 1];
+  __shared__ uint32_t s_off[TP];
+  __shared__ uint32_t ws[4];
+  __shared__ float s_gam[NF];
+  __shared__ uint8_t s_ent[NF];
+  __shared__ float2 s_bst[NF];
+  __shared__ float4 s_desc[FINE_E][D / 4];
   const int t = threadIdx.x;
-  const uint32_t nf = info[4];
-  const uint32_t f0 = blockIdx.x * FINE_PER_WG;
-  if (f0 >= nf) return;
-  const uint32_t f1 = min(f0 + FINE_PER_WG, nf);
-  uint4 wk = fine_work[f0];
-  bool has = wk.y + uint32_t(t) < wk.z;
+  const uint4 wk = fine_work[blockIdx.x];  // in bounds (grid = bin count); used only if valid
+  if (blockIdx.x >= info[4]) return;
+  const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z;
+  const BinInfo bi = decode_bin(P, b);
+  const bool has = e0 + uint32_t(t) < e1;
   Entry en = {};
-  if (has) en = ent[wk.y + t];
-  for (uint32_t f = f0; f < f1; ++f) {
-    const uint4 wn = f + 1 < f1 ? fine_work[f + 1] : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t b = wk.x;
-    const BinInfo bi = decode_bin(P, b);
-    {  // upstream gradient of the tile's texels inside the layer
-      const int lth = 8 - P.ltw;
-      const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
-      const int j = (bi.ty << lth) + (t >> P.ltw);
-      if (i < bi.WL && j < bi.HL) {
-        const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+  if (has) en = ent[e0 + t];
+  const uint32_t k = min(npix[size_t(b) * TP + t], uint32_t(KEEP));
+  {  // upstream gradient of the tile's texels inside the layer
+    const int lth = 8 - P.ltw;
+    const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+    const int j = (bi.ty << lth) + (t >> P.ltw);
+    if (i < bi.WL && j < bi.HL) {
+      const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
 #pragma unroll
-        for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
-      }
+      for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
     }
-    __syncthreads();
-    const bool has_n = wn.y + uint32_t(t) < wn.z;
-    Entry enn = {};
-    if (has_n) enn = ent[wn.y + t];
-    if (has) {
-      Corner cs[4];
-      uint32_t cm = entry_corners(en, bi, P.ltw, cs);
-      const uint32_t packed = en.slot >> KSLOT_SHIFT;
-      size_t pos[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t m = (packed >> (5 * q)) & 31u;
-        pos[q] = 0;
-        if (((cm >> q) & 1u) && m < KEEP) pos[q] = (size_t(b) * KEEP + m) * TP + uint32_t(cs[q].p);
-        else cm &= ~(1u << q);
-      }
-      float2 st[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) st[q] = ((cm >> q) & 1u) ? bst[pos[q]] : make_float2(0.f, 0.f);
-      float A = 0.0f, Bx = 0.0f, By = 0.0f;
-      float tau[D];
-#pragma unroll
-      for (int d = 0; d < D; ++d) tau[d] = 0.0f;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!((cm >> q) & 1u)) continue;
-        const int p = cs[q].p;
-        const float dg = st[q].x;
-        A += dg * (cs[q].wx * cs[q].wy);
-        Bx += dg * (cs[q].sx * cs[q].wy);
-        By += dg * (cs[q].wx * cs[q].sy);
-#pragma unroll
-        for (int d = 0; d < D; ++d) tau[d] += st[q].y * s_G[p][d];
-      }
-      float* r = rows + ((size_t(bi.v) * NSLOT + (en.slot & 7u)) * size_t(P.n) + en.idx) * RW;
-      float4* r4 = reinterpret_cast<float4*>(r);
-      r4[0] = make_float4(A, Bx, By, 0.0f);
-#pragma unroll
-      for (int q = 0; q < D / 4; ++q)
-        r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
-    }
-    wk = wn;
-    has = has_n;
-    en = enn;
-    __syncthreads();  // s_G is reused by the next tile
   }
+  float4 dv[D / 4];
+#pragma unroll
+  for (int r4 = 0; r4 < D / 4; ++r4) dv[r4] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (has) {
+    const float4* dp = reinterpret_cast<const float4*>(desc + size_t(en.idx) * D);
+#pragma unroll
+    for (int r4 = 0; r4 < D / 4; ++r4) dv[r4] = dp[r4];
+  }
+  uint32_t kt;
+  s_off[t] = block_excl_scan<4>(k, ws, kt);
+#pragma unroll
+  for (int r4 = 0; r4 < D / 4; ++r4) s_desc[t][r4] = dv[r4];
+  __syncthreads();
+  Corner cs[4];
+  uint32_t cm = has ? entry_corners(en, bi, P.ltw, cs) : 0u;
+  const uint32_t packed = en.slot >> KSLOT_SHIFT;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t m = (packed >> (5 * q)) & 31u;
+    if (((cm >> q) & 1u) && m < KEEP) {
+      const uint32_t o = s_off[cs[q].p] + m;
+      s_gam[o] = (cs[q].wx * cs[q].wy) * en.ia;
+      s_ent[o] = uint8_t(t);
+    } else {
+      cm &= ~(1u << q);
+    }
+  }
+  __syncthreads();
+  if (k > 0) {  // blend adjoint of texel t
+    const uint32_t o0 = s_off[t];
+    float G[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) G[d] = s_G[t][d];
+    float T = 1.0f;
+    for (uint32_t m = 0; m < k; ++m) {  // front to back: T_m and g_m
+      float4 tv[D / 4];
+#pragma unroll
+      for (int r4 = 0; r4 < D / 4; ++r4) tv[r4] = s_desc[s_ent[o0 + m]][r4];
+      s_bst[o0 + m] = make_float2(dot_g<D>(G, tv), T);
+      T = T * (1.0f - s_gam[o0 + m]);
+    }
+    float B = 0.0f;
+    for (uint32_t m = k; m-- > 0;) {  // back to front
+      const float2 gt = s_bst[o0 + m];
+      s_bst[o0 + m] = blend_adjoint_step(gt.y, s_gam[o0 + m], gt.x, B);
+    }
+  }
+  __syncthreads();
+  if (!has) return;
+  float2 st[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    st[q] = ((cm >> q) & 1u) ? s_bst[s_off[cs[q].p] + ((packed >> (5 * q)) & 31u)] : make_float2(0.f, 0.f);
+  float A = 0.0f, Bx = 0.0f, By = 0.0f;
+  float tau[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) tau[d] = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!((cm >> q) & 1u)) continue;
+    const int p = cs[q].p;
+    const float dg = st[q].x;
+    A += dg * (cs[q].wx * cs[q].wy);
+    Bx += dg * (cs[q].sx * cs[q].wy);
+    By += dg * (cs[q].wx * cs[q].sy);
+#pragma unroll
+    for (int d = 0; d < D; ++d) tau[d] += st[q].y * s_G[p][d];
+  }
+  float* r = rows + ((size_t(bi.v) * NSLOT + (en.slot & 7u)) * size_t(P.n) + en.idx) * RW;
+  float4* r4 = reinterpret_cast<float4*>(r);
+  r4[0] = make_float4(A, Bx, By, 0.0f);
+#pragma unroll
+  for (int q = 0; q < D / 4; ++q)
+    r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
 }
 
 // bwd_points: per point, every view: read the rows of its entries, apply the layer and
@@ -1477,8 +1511,8 @@ struct Layout {
   uint64_t icap;      // work-item capacity
   uint64_t npyr;      // texels of all views and layers
   // saved buffer
-  size_t s_info, s_bin_start, s_item_start, s_multi, s_fine, s_npix, s_kkey, s_kgam, s_tables_end,
-      s_work, s_ent;
+  size_t s_info, s_bin_start, s_item_start, s_multi, s_fine, s_coarse, s_npix, s_kkey, s_kgam,
+      s_tables_end, s_work, s_ent;
   size_t saved_bytes;
   // workspace
   size_t w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, ws_bytes;
@@ -1567,6 +1601,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.s_item_start = take((NB + 1) * 4);
   lay.s_multi = take(NB * 4);
   lay.s_fine = take(NB * sizeof(uint4));
+  lay.s_coarse = take(NB * 4);
   // texel tables: their offsets depend only on the cameras and config (export reads them)
   lay.s_npix = take(NB * TP * 4);
   lay.s_kkey = take(NB * TP * KEEP * 8);
@@ -1626,6 +1661,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   uint4* work = reinterpret_cast<uint4*>(sv + lay.s_work);
   uint32_t* multi_bins = reinterpret_cast<uint32_t*>(sv + lay.s_multi);
   uint4* fine_work = reinterpret_cast<uint4*>(sv + lay.s_fine);
+  uint32_t* coarse_bins = reinterpret_cast<uint32_t*>(sv + lay.s_coarse);
   uint32_t* npix = reinterpret_cast<uint32_t*>(sv + lay.s_npix);
   uint64_t* kkey = reinterpret_cast<uint64_t*>(sv + lay.s_kkey);
   float* kgam = reinterpret_cast<float*>(sv + lay.s_kgam);
@@ -1649,7 +1685,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   {
     StageTimer tm(ST_BINSCAN, st);
     hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, tot, bin_start, item_start,
-                       multi_bins, fine_work, info, P.NB, P.item_e);
+                       multi_bins, fine_work, coarse_bins, info, P.NB, P.item_e);
   }
   TRIPS_HIP(hipGetLastError());
   {
@@ -1678,8 +1714,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   TRIPS_HIP(hipGetLastError());
   {  // one workgroup per fine tile; workgroups beyond their count exit at once
     StageTimer tm(ST_FWD_FINE, st);
-    hipLaunchKernelGGL(k_fwd_fine<D>, dim3((P.NB + FINE_PER_WG - 1) / FINE_PER_WG), dim3(256), 0,
-                       st, P, info, fine_work, ent,
+    hipLaunchKernelGGL(k_fwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent,
                        pts.desc, pyr, npix, kkey, kgam);
   }
   TRIPS_HIP(hipGetLastError());
@@ -1702,6 +1737,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   const uint32_t* info = reinterpret_cast<const uint32_t*>(sv + lay.s_info);
   const uint4* work = reinterpret_cast<const uint4*>(sv + lay.s_work);
   const uint4* fine_work = reinterpret_cast<const uint4*>(sv + lay.s_fine);
+  const uint32_t* coarse_bins = reinterpret_cast<const uint32_t*>(sv + lay.s_coarse);
   const uint32_t* npix = reinterpret_cast<const uint32_t*>(sv + lay.s_npix);
   const uint64_t* kkey = reinterpret_cast<const uint64_t*>(sv + lay.s_kkey);
   const float* kgam = reinterpret_cast<const float*>(sv + lay.s_kgam);
@@ -1709,8 +1745,8 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
 
   {
     StageTimer tm(ST_BWD_PIXELS, st);
-    hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, npix, kkey, kgam, pts.desc,
-                       gpyr, bst);
+    hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
+                       kkey, kgam, pts.desc, gpyr, bst);
   }
   TRIPS_HIP(hipGetLastError());
   {
@@ -1721,8 +1757,8 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BWD_FINE, st);
-    hipLaunchKernelGGL(k_bwd_fine<D>, dim3((P.NB + FINE_PER_WG - 1) / FINE_PER_WG), dim3(256), 0,
-                       st, P, info, fine_work, ent, bst, gpyr, rows);
+    hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent, npix,
+                       pts.desc, gpyr, rows);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.n > 0) {
