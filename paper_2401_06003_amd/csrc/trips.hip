@@ -345,11 +345,20 @@ __global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const flo
   __syncthreads();
   const int64_t p0 = int64_t(blk) * P.pb;
   const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    for_each_entry(P, c, X[p], Y[p], Z[p], SW[p],
+  // the next point of this thread is loaded while the current one is binned (the index is
+  // clamped to the block's last point, a valid address)
+  int64_t p = p0 + threadIdx.x;
+  int64_t pc = min(p, p1 - 1);
+  float x = 0.f, y = 0.f, z = 0.f, sw = 0.f;
+  if (p < p1) { x = X[pc]; y = Y[pc]; z = Z[pc]; sw = SW[pc]; }
+  for (; p < p1; p += blockDim.x) {
+    pc = min(p + int64_t(blockDim.x), p1 - 1);
+    const float xn = X[pc], yn = Y[pc], zn = Z[pc], swn = SW[pc];
+    for_each_entry(P, c, x, y, z, sw,
                    [&](uint32_t bin, uint32_t, int, const Foot&, const Geo&) {
                      add16(hist, bin - c.bin_base);
                    });
+    x = xn; y = yn; z = zn; sw = swn;
   }
   __syncthreads();
   uint32_t* row = H + size_t(blk) * P.NB + c.bin_base;
@@ -511,16 +520,33 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
   const uint32_t* bs = bin_start + c.bin_base;
   if (threadIdx.x == 0) s_vis = 0;
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) hist[i] = 0;
-  if (STAGED)
-    for (uint32_t i = threadIdx.x; i < c.nbins; i += blockDim.x) base[i] = bs[i] + row[i];
+  if (STAGED)  // four bins per thread in flight
+    for (uint32_t i0 = threadIdx.x; i0 < c.nbins; i0 += 4 * blockDim.x) {
+      uint32_t v4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = min(i0 + q * blockDim.x, c.nbins - 1);  // a valid bin, used if in range
+        v4[q] = bs[i] + row[i];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (i0 + q * blockDim.x < c.nbins) base[i0 + q * blockDim.x] = v4[q];
+    }
   __syncthreads();
   const int64_t p0 = int64_t(blk) * P.pb;
   const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
   uint32_t vis = 0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    const float alpha = A[p];
+  // one point ahead, as in the count pass
+  int64_t pn = p0 + threadIdx.x;
+  int64_t pc = min(pn, p1 - 1);
+  float x = 0.f, y = 0.f, z = 0.f, sw = 0.f, al = 0.f;
+  if (pn < p1) { x = X[pc]; y = Y[pc]; z = Z[pc]; sw = SW[pc]; al = A[pc]; }
+  for (int64_t p = pn; p < p1; p += blockDim.x) {
+    pc = min(p + int64_t(blockDim.x), p1 - 1);
+    const float xn = X[pc], yn = Y[pc], zn = Z[pc], swn = SW[pc], aln = A[pc];
+    const float alpha = al;
     bool any = false;
-    for_each_entry(P, c, X[p], Y[p], Z[p], SW[p],
+    for_each_entry(P, c, x, y, z, sw,
                    [&](uint32_t bin, uint32_t slot, int sel, const Foot& ft, const Geo& g) {
                      any = true;
                      const uint32_t lb = bin - c.bin_base;
@@ -535,6 +561,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
                      ent[(STAGED ? base[lb] : bs[lb] + row[lb]) + rank] = e;
                    });
     vis += any ? 1u : 0u;
+    x = xn; y = yn; z = zn; sw = swn; al = aln;
   }
   // number of (point, view) pairs with at least one entry, for reports
   atomicAdd(&s_vis, vis);
@@ -633,6 +660,31 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
 constexpr int EPT = 2;                // entries per thread per LDS round
 constexpr int SUB_E = EPT * TP;       // entries per LDS round
 constexpr int SUB_F = 4 * SUB_E;      // fragments per LDS round (at most 4 per entry)
+
+// Compare-exchange of (key, gamma) pairs: afterwards a holds the smaller key.
+__device__ __forceinline__ void cswap(uint64_t& ka, float& ga, uint64_t& kb, float& gb) {
+  const bool sw = kb < ka;
+  const uint64_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+  const float g0 = sw ? gb : ga, g1 = sw ? ga : gb;
+  ka = k0; kb = k1; ga = g0; gb = g1;
+}
+
+// Lowest 16 of two ascending lists: c[i] = min(a[i], b[15-i]) is bitonic and holds them;
+// half-cleaners of width 8, 4, 2, 1 sort it.
+__device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
+                                        const uint64_t (&ok)[KEEP], const float (&og)[KEEP]) {
+#pragma unroll
+  for (int i = 0; i < KEEP; ++i) {
+    const bool take = ok[KEEP - 1 - i] < k[i];
+    k[i] = take ? ok[KEEP - 1 - i] : k[i];
+    g[i] = take ? og[KEEP - 1 - i] : g[i];
+  }
+#pragma unroll
+  for (int w = KEEP / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int i = 0; i < KEEP; ++i)
+      if ((i & w) == 0) cswap(k[i], g[i], k[i + w], g[i + w]);
+}
 
 // item_bins: the work table in processing order, largest items first (size classes of
 // item_e / NBUCKET entries; the order within a class is whatever the atomics give, which
@@ -905,7 +957,7 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
       float T = 1.0f;
 #pragma unroll 1
       for (uint32_t m = 0; m < k; ++m) {
-        const uint32_t o = base + sord[base + m];
+        const uint32_t o = base + min(uint32_t(sord[base + m]), cnt - 1);  // guards LDS only
         const uint64_t kq = skey[o];
         const float gq = sgam[o];
         const uint32_t eo = sent[o];
@@ -931,31 +983,6 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
       npix[size_t(b) * TP + t] = cnt;
     }
   }
-}
-
-// Compare-exchange of (key, gamma) pairs: afterwards a holds the smaller key.
-__device__ __forceinline__ void cswap(uint64_t& ka, float& ga, uint64_t& kb, float& gb) {
-  const bool sw = kb < ka;
-  const uint64_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
-  const float g0 = sw ? gb : ga, g1 = sw ? ga : gb;
-  ka = k0; kb = k1; ga = g0; gb = g1;
-}
-
-// Lowest 16 of two ascending lists: c[i] = min(a[i], b[15-i]) is bitonic and holds them;
-// half-cleaners of width 8, 4, 2, 1 sort it.
-__device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
-                                        const uint64_t (&ok)[KEEP], const float (&og)[KEEP]) {
-#pragma unroll
-  for (int i = 0; i < KEEP; ++i) {
-    const bool take = ok[KEEP - 1 - i] < k[i];
-    k[i] = take ? ok[KEEP - 1 - i] : k[i];
-    g[i] = take ? og[KEEP - 1 - i] : g[i];
-  }
-#pragma unroll
-  for (int w = KEEP / 2; w >= 1; w >>= 1)
-#pragma unroll
-    for (int i = 0; i < KEEP; ++i)
-      if ((i & w) == 0) cswap(k[i], g[i], k[i + w], g[i + w]);
 }
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
@@ -1174,9 +1201,14 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     s_k[t] = k;
     uint64_t last = 0;
     uint32_t ids[KEEP];
+    uint64_t raw[KEEP];
+    // all 16 loads are issued together: slots past the list read slot 0 of the same texel
+    // (a valid address) and are discarded
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) raw[m] = kkey[(size_t(b) * KEEP + (uint32_t(m) < k ? m : 0)) * TP + t];
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) {
-      const uint64_t key = uint32_t(m) < k ? kkey[(size_t(b) * KEEP + m) * TP + t] : KEY_NONE;
+      const uint64_t key = uint32_t(m) < k ? raw[m] : KEY_NONE;
       ids[m] = uint32_t(key);
       last = uint32_t(m) < k ? key : last;
     }
