@@ -88,6 +88,27 @@ typedef struct {
   int32_t item_entries;
 } trips_tuning;
 
+/* Optional arguments of trips_forward, trips_backward and trips_plan_create (pass NULL, or
+   NULL fields, for none; each call takes the fields of its direction).  Device pointers in
+   pyramid order (P texels of all views and layers, the pyramid's order), [P][D] arrays
+   row-major per texel and 16-byte aligned.
+   - background [P][D] (forward and backward): composited behind each texel's kept
+     fragments with the transmittance they leave, C += T_K * background, T_K =
+     prod_m (1 - gamma_m) over the kept list.  This is where the environment map E of Eq. 1
+     enters; the caller samples it per texel.
+   - alpha_out [P] (forward output): the coverage 1 - T_K of every texel.
+   - grad_alpha [P] (backward input): upstream gradient of alpha_out.
+   - grad_background [P][D] (backward output): T_K * grad_pyramid.
+   - grad_camera [views][16] (backward output): per view dL/dR (9, row-major, for
+     X_c = R X_w + t), dL/dt (3), dL/dfx, dL/dfy, dL/dcx, dL/dcy. */
+typedef struct {
+  const float* background;
+  float* alpha_out;
+  const float* grad_alpha;
+  float* grad_background;
+  float* grad_camera;
+} trips_extras;
+
 /* Host only.  Layer sizes of one view: dims_host[2L] = W_L, dims_host[2L+1] = H_L, and
    offsets_host[L] = first texel of layer L in the concatenated pyramid of that view,
    offsets_host[num_layers] = total texels.  Either output may be NULL. */
@@ -109,7 +130,7 @@ trips_status trips_forward(const trips_config* cfg_host, const trips_points* pts
                            const trips_camera* cams_host, int32_t views,
                            const trips_tuning* tuning_host, float* pyramid_out, void* saved,
                            size_t saved_bytes, void* workspace, size_t workspace_bytes,
-                           hipStream_t stream);
+                           const trips_extras* extras_host, hipStream_t stream);
 
 /* Backward of sum(grad_pyramid * pyramid) for the forward call that filled `saved`
    (same points, cameras, config and tuning).  grad_pyramid has the pyramid layout.
@@ -123,7 +144,7 @@ trips_status trips_backward(const trips_config* cfg_host, const trips_points* pt
                             const void* saved, size_t saved_bytes, void* workspace,
                             size_t workspace_bytes, float* grad_x, float* grad_y, float* grad_z,
                             float* grad_size_w, float* grad_opacity, float* grad_desc,
-                            hipStream_t stream);
+                            const trips_extras* extras_host, hipStream_t stream);
 
 /* Parity export of the fragment lists of the forward call that filled `saved`.
    counts: int32 [P] untruncated list length per texel; ids: int32 [P][16] kept point
@@ -198,7 +219,8 @@ trips_status trips_plan_create(const trips_config* cfg_host, const trips_points*
                                size_t saved_bytes, void* workspace, size_t workspace_bytes,
                                const float* grad_pyramid, float* grad_x, float* grad_y,
                                float* grad_z, float* grad_size_w, float* grad_opacity,
-                               float* grad_desc, hipStream_t stream, trips_plan** plan_out);
+                               float* grad_desc, const trips_extras* extras_host,
+                               hipStream_t stream, trips_plan** plan_out);
 /* which: 1 = forward, 2 = backward, 3 = both (in that order). */
 trips_status trips_plan_launch(trips_plan* plan, int32_t which, hipStream_t stream);
 void trips_plan_destroy(trips_plan* plan);

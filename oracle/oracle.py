@@ -82,6 +82,14 @@ def _configure(L):
         L.oracle_backward.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int, c_int,
                                       c_int, c_double, c_int, u8p, dp, dp, dp, dp, dp, dp, dp]
         L.oracle_backward.restype = c_int
+        L.oracle_forward_ex.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int,
+                                        c_int, c_int, c_double, c_int, u8p, u8p, dp, i32p, i64p,
+                                        u8p]
+        L.oracle_forward_ex.restype = c_int
+        L.oracle_backward_ex.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int,
+                                         c_int, c_int, c_double, c_int, u8p, u8p, dp, u8p, dp, dp,
+                                         dp, dp, dp, dp, u8p, u8p]
+        L.oracle_backward_ex.restype = c_int
     return L
 
 
@@ -195,6 +203,69 @@ def backward(pts, cam, nlayers, G, maxlist=16, eps=0.25, fp32=True, mask=None):
                                float(eps), int(fp32), mp, _ptr(Gd), _ptr(out["gx"]), _ptr(out["gy"]),
                                _ptr(out["gz"]), _ptr(out["gsw"]), _ptr(out["galpha"]),
                                _ptr(out["gdesc"]))
+    assert rc == 0, rc
+    return out
+
+
+def _opt(a):
+    """(keep-alive array, void pointer) of an optional float64 array."""
+    if a is None:
+        return None, ctypes.c_void_p(0)
+    a = _d(a)
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+def forward_ex(pts, cam, nlayers, background=None, maxlist=16, eps=0.25, fp32=True, mask=None):
+    """forward() with the optional terms: background [P, D] composited behind the kept
+    list with the transmittance it leaves.  Returns dict pyr [P, D], counts, ids and alpha
+    [P] (the coverage 1 - T_K)."""
+    n = len(pts["x"])
+    X, Y, Z, S, A = (_d(pts[k]) for k in ("x", "y", "z", "sw", "alpha"))
+    desc = _d(pts["desc"]).reshape(n, -1) if n else np.zeros((0, pts["desc"].shape[-1]))
+    D = desc.shape[1]
+    cv = cam_vector(cam)
+    P = num_pixels(cam["W"], cam["H"], nlayers)
+    out = {"pyr": np.zeros((P, D)), "counts": np.zeros(P, dtype=np.int32),
+           "ids": np.zeros((P, maxlist), dtype=np.int64), "alpha": np.zeros(P)}
+    keep, mp = _mask_ptr(mask, P)
+    bgk, bgp = _opt(None if background is None else np.asarray(background).reshape(P, D))
+    rc = lib().oracle_forward_ex(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(S), _ptr(A), _ptr(desc), D,
+                                 _ptr(cv), int(cam["W"]), int(cam["H"]), int(nlayers),
+                                 int(maxlist), float(eps), int(fp32), mp, bgp, _ptr(out["pyr"]),
+                                 _ptr(out["counts"], ctypes.c_int32),
+                                 _ptr(out["ids"], ctypes.c_int64),
+                                 ctypes.c_void_p(out["alpha"].ctypes.data))
+    assert rc == 0, rc
+    return out
+
+
+def backward_ex(pts, cam, nlayers, G, background=None, grad_alpha=None, maxlist=16, eps=0.25,
+                fp32=True, mask=None):
+    """backward() with the optional terms: the background the forward composited, the
+    upstream gradient of the coverage, and the gradients of the background (gbg [P, D])
+    and of the camera (gcam [16]: dR row-major, dt, dfx, dfy, dcx, dcy)."""
+    n = len(pts["x"])
+    X, Y, Z, S, A = (_d(pts[k]) for k in ("x", "y", "z", "sw", "alpha"))
+    desc = _d(pts["desc"]).reshape(n, -1)
+    D = desc.shape[1]
+    cv = cam_vector(cam)
+    Gd = _d(G).reshape(-1, D)
+    P = Gd.shape[0]
+    assert P == num_pixels(cam["W"], cam["H"], nlayers)
+    out = {k: np.zeros(n) for k in ("gx", "gy", "gz", "gsw", "galpha")}
+    out["gdesc"] = np.zeros((n, D))
+    out["gbg"] = np.zeros((P, D))
+    out["gcam"] = np.zeros(16)
+    keep, mp = _mask_ptr(mask, P)
+    bgk, bgp = _opt(None if background is None else np.asarray(background).reshape(P, D))
+    gak, gap = _opt(None if grad_alpha is None else np.asarray(grad_alpha).reshape(P))
+    rc = lib().oracle_backward_ex(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(S), _ptr(A), _ptr(desc), D,
+                                  _ptr(cv), int(cam["W"]), int(cam["H"]), int(nlayers),
+                                  int(maxlist), float(eps), int(fp32), mp, bgp, _ptr(Gd), gap,
+                                  _ptr(out["gx"]), _ptr(out["gy"]), _ptr(out["gz"]),
+                                  _ptr(out["gsw"]), _ptr(out["galpha"]), _ptr(out["gdesc"]),
+                                  ctypes.c_void_p(out["gbg"].ctypes.data),
+                                  ctypes.c_void_p(out["gcam"].ctypes.data))
     assert rc == 0, rc
     return out
 

@@ -22,6 +22,11 @@
  *   The backward pass is the analytic adjoint of steps 3-5 and of the projection,
  *   differentiated with respect to positions, world sizes, opacities and
  *   descriptors (the paper states the pipeline is differentiable in all four).
+ *   The _ex entry points add the optional terms: a background composited behind the
+ *   kept fragments (C += T_K bg, T_K the transmittance left after the kept list; the
+ *   environment map E of Eq. 1 sampled per texel), the coverage 1 - T_K of every texel,
+ *   and the gradients with respect to the background and to the camera (R, t, fx, fy,
+ *   cx, cy of Eq. 2).
  *
  * Precision.  Two modes:
  *   fp32 = 1: the projection and every decision that picks an integer (culling,
@@ -46,7 +51,9 @@
  *     are non-zero; no renormalisation at borders.
  *   - depth is camera-space z, ascending; ties by point index ascending.
  *   - the alpha of Eq. 6 is the fragment's gamma; the colour is the descriptor.
- *   - no background term: an empty list gives 0.
+ *   - without a background an empty list gives 0; with one, the background is seen
+ *     through the transmittance the kept fragments leave (an empty list shows it whole).
+ *   - the coverage output is 1 - T_K over the kept list (the blend of a constant 1).
  *   - f in Eq. 2 is f_x; points with z <= znear or non-finite x, y, s are culled.
  *
  * Compile with -O2 -ffp-contract=off and without -ffast-math.
@@ -245,6 +252,7 @@ static frag_t* collect(int64_t n, const double* X, const double* Y, const double
 }
 
 static int check_args(int64_t n, int D, int W, int H, int nlayers, int maxlist) {
+  if (D > 64) return 0;
   if (n < 0 || D < 1 || W < 1 || H < 1 || nlayers < 1 || nlayers > 30 || maxlist < 1) return 0;
   return 1;
 }
@@ -305,18 +313,27 @@ int64_t oracle_fragments(int64_t n, const double* X, const double* Y, const doub
 /* Forward, one view.  pyr: [sum_L H_L W_L][D] (layers concatenated, each row-major);
    counts: untruncated list length per texel; ids: [P][maxlist] kept point indices in
    blend order, -1 padded.  mask (optional, [P] bytes): only texels with a non-zero
-   mask byte are evaluated; the others are left at 0 / -1. */
-int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z, const double* SW,
-                   const double* A, const double* DESC, int D, const double* cam, int W, int H,
-                   int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
-                   double* pyr, int32_t* counts, int64_t* ids) {
+   mask byte are evaluated; the others are left at 0 / -1.  bg (optional, [P][D]):
+   background composited behind the kept list; alpha (optional, [P]): coverage
+   1 - T_K.  Texels outside the mask keep bg = 0 and alpha = 0 too. */
+int oracle_forward_ex(int64_t n, const double* X, const double* Y, const double* Z,
+                      const double* SW, const double* A, const double* DESC, int D,
+                      const double* cam, int W, int H, int nlayers, int maxlist, double eps,
+                      int fp32, const uint8_t* mask, const double* bg, double* pyr,
+                      int32_t* counts, int64_t* ids, double* alpha) {
   if (!check_args(n, D, W, H, nlayers, maxlist)) return OR_ERR_ARG;
   cam_t c;
   unpack_cam(cam, W, H, &c);
   int64_t P = oracle_num_pixels(W, H, nlayers);
   memset(pyr, 0, (size_t)P * D * sizeof(double));
   memset(counts, 0, (size_t)P * sizeof(int32_t));
+  if (alpha) memset(alpha, 0, (size_t)P * sizeof(double));
   for (int64_t k = 0; k < P * maxlist; ++k) ids[k] = -1;
+  /* an empty list shows the whole background */
+  if (bg)
+    for (int64_t pix = 0; pix < P; ++pix)
+      if (!mask || mask[pix])
+        for (int d = 0; d < D; ++d) pyr[pix * D + d] = bg[pix * D + d];
   int64_t nf = 0;
   frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, mask, &nf, NULL);
   if (!fr) return OR_ERR_MEM;
@@ -329,35 +346,52 @@ int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z,
     counts[pix] = (int32_t)len;
     int64_t keep = len < maxlist ? len : maxlist;
     double T = 1.0;
+    double col[64];
+    for (int d = 0; d < D; ++d) col[d] = 0.0;
     for (int64_t m = 0; m < keep; ++m) {
       const frag_t* f = &fr[a + m];
       ids[pix * maxlist + m] = f->idx;
       double w = T * f->gamma;
       for (int d = 0; d < D; ++d) {
         double tau = fp32 ? (double)(float)DESC[f->idx * D + d] : DESC[f->idx * D + d];
-        pyr[pix * D + d] += w * tau;
+        col[d] += w * tau;
       }
       T = T * (1.0 - f->gamma);
     }
+    for (int d = 0; d < D; ++d) pyr[pix * D + d] = col[d] + (bg ? T * bg[pix * D + d] : 0.0);
+    if (alpha) alpha[pix] = 1.0 - T;
     a = b;
   }
   free(fr);
   return OR_OK;
 }
 
-/* Backward, one view: gradients of sum(G * pyr) with respect to X, Y, Z, SW, A and DESC.
+int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z, const double* SW,
+                   const double* A, const double* DESC, int D, const double* cam, int W, int H,
+                   int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
+                   double* pyr, int32_t* counts, int64_t* ids) {
+  return oracle_forward_ex(n, X, Y, Z, SW, A, DESC, D, cam, W, H, nlayers, maxlist, eps, fp32,
+                           mask, NULL, pyr, counts, ids, NULL);
+}
+
+/* Backward, one view: gradients of sum(G * pyr) (+ sum(Galpha * alpha) when Galpha is
+   given) with respect to X, Y, Z, SW, A and DESC; with bg, the background the forward
+   composited; gbg (optional, [P][D]) receives dL/dbg = T_K G and gcam (optional, [16])
+   the camera gradient: dL/dR (row-major), dL/dt, dL/dfx, dL/dfy, dL/dcx, dL/dcy.
    Outputs are overwritten.  The depth order, culling and the 16-element clamp are
    piecewise constant and carry no gradient; fragments beyond the clamp get none.
    mask (optional): only texels with a non-zero mask byte contribute, so a point's
    gradient is exact when every texel it writes is in the mask. */
-int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z, const double* SW,
-                    const double* A, const double* DESC, int D, const double* cam, int W, int H,
-                    int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
-                    const double* G, double* gX, double* gY, double* gZ, double* gSW, double* gA,
-                    double* gDESC) {
+int oracle_backward_ex(int64_t n, const double* X, const double* Y, const double* Z,
+                       const double* SW, const double* A, const double* DESC, int D,
+                       const double* cam, int W, int H, int nlayers, int maxlist, double eps,
+                       int fp32, const uint8_t* mask, const double* bg, const double* G,
+                       const double* Galpha, double* gX, double* gY, double* gZ, double* gSW,
+                       double* gA, double* gDESC, double* gbg, double* gcam) {
   if (!check_args(n, D, W, H, nlayers, maxlist)) return OR_ERR_ARG;
   cam_t c;
   unpack_cam(cam, W, H, &c);
+  int64_t P = oracle_num_pixels(W, H, nlayers);
   int64_t nf = 0;
   proj_t* pr = NULL;
   frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, mask, &nf, &pr);
@@ -369,6 +403,13 @@ int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z
   if (!gxs || !gys || !gss || !Tm) { free(fr); free(pr); free(gxs); free(gys); free(gss); free(Tm); return OR_ERR_MEM; }
   memset(gA, 0, (size_t)n * sizeof(double));
   memset(gDESC, 0, (size_t)n * D * sizeof(double));
+  if (gcam) memset(gcam, 0, 16 * sizeof(double));
+  if (gbg) {  /* an empty list shows the whole background: dL/dbg = G */
+    memset(gbg, 0, (size_t)P * D * sizeof(double));
+    for (int64_t pix = 0; pix < P; ++pix)
+      if (!mask || mask[pix])
+        for (int d = 0; d < D; ++d) gbg[pix * D + d] = G[pix * D + d];
+  }
   int64_t a = 0;
   while (a < nf) {
     int64_t b = a;
@@ -379,11 +420,17 @@ int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z
     const double* g = &G[pix * D];
     double T = 1.0;
     for (int64_t m = 0; m < keep; ++m) { Tm[m] = T; T = T * (1.0 - fr[a + m].gamma); }
-    /* Reverse sweep.  With g_m = G . tau_m, the colour is C.G = sum_m T_m gamma_m g_m;
-       B_m = sum_{i>m} (T_i / T_{m+1}) gamma_i g_i is the normalised tail behind m,
-       built back to front: B_last = 0, B_{m-1} = gamma_m g_m + (1 - gamma_m) B_m.
-       Then dC.G/dgamma_m = T_m (g_m - B_m), with no division by (1 - gamma). */
+    if (gbg)
+      for (int d = 0; d < D; ++d) gbg[pix * D + d] = T * g[d];
+    /* Reverse sweep.  With g_m = G . tau_m (+ Galpha: the coverage blends a constant 1),
+       the output is C.G = sum_m T_m gamma_m g_m + T_K (G . bg);
+       B_m = sum_{i>m} (T_i / T_{m+1}) gamma_i g_i + (T_K / T_{m+1}) G . bg is the
+       normalised tail behind m, built back to front: B_last = G . bg,
+       B_{m-1} = gamma_m g_m + (1 - gamma_m) B_m.  Then dC.G/dgamma_m = T_m (g_m - B_m),
+       with no division by (1 - gamma). */
     double B = 0.0;
+    if (bg)
+      for (int d = 0; d < D; ++d) B += g[d] * bg[pix * D + d];
     for (int64_t m = keep - 1; m >= 0; --m) {
       const frag_t* f = &fr[a + m];
       int64_t p = f->idx;
@@ -392,6 +439,7 @@ int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z
         double tau = fp32 ? (double)(float)DESC[p * D + d] : DESC[p * D + d];
         gm += g[d] * tau;
       }
+      if (Galpha) gm += Galpha[pix];
       double w = Tm[m] * f->gamma;
       for (int d = 0; d < D; ++d) gDESC[p * D + d] += w * g[d];
       double dgam = Tm[m] * (gm - B);
@@ -425,7 +473,32 @@ int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z
     gY[p] = R[1] * dXc + R[4] * dYc + R[7] * dZc;
     gZ[p] = R[2] * dXc + R[5] * dYc + R[8] * dZc;
     gSW[p] = gss[p] * fx / Zc;
+    if (gcam) {
+      /* X_c = R X_w + t: dL/dR_rc = dL/dX_c[r] X_w[c], dL/dt = dL/dX_c;
+         x = fx X_c/Z_c + cx, y = fy Y_c/Z_c + cy, s = fx s_w / Z_c */
+      double Xw[3], dX[3] = {dXc, dYc, dZc};
+      Xw[0] = fp32 ? (double)(float)X[p] : X[p];
+      Xw[1] = fp32 ? (double)(float)Y[p] : Y[p];
+      Xw[2] = fp32 ? (double)(float)Z[p] : Z[p];
+      double sw = fp32 ? (double)(float)SW[p] : SW[p];
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) gcam[3 * r + k] += dX[r] * Xw[k];
+      for (int r = 0; r < 3; ++r) gcam[9 + r] += dX[r];
+      gcam[12] += gxs[p] * q->Xc / Zc + gss[p] * sw / Zc;
+      gcam[13] += gys[p] * q->Yc / Zc;
+      gcam[14] += gxs[p];
+      gcam[15] += gys[p];
+    }
   }
   free(fr); free(pr); free(gxs); free(gys); free(gss); free(Tm);
   return OR_OK;
+}
+
+int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z, const double* SW,
+                    const double* A, const double* DESC, int D, const double* cam, int W, int H,
+                    int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
+                    const double* G, double* gX, double* gY, double* gZ, double* gSW, double* gA,
+                    double* gDESC) {
+  return oracle_backward_ex(n, X, Y, Z, SW, A, DESC, D, cam, W, H, nlayers, maxlist, eps, fp32,
+                            mask, NULL, G, NULL, gX, gY, gZ, gSW, gA, gDESC, NULL, NULL);
 }

@@ -34,6 +34,12 @@ class Points(ctypes.Structure):
                 ("opacity", c_void_p), ("desc", c_void_p), ("n", c_int64)]
 
 
+class Extras(ctypes.Structure):
+    """Optional arguments (trips_extras): background, coverage, their gradients, camera grads."""
+    _fields_ = [("background", c_void_p), ("alpha_out", c_void_p), ("grad_alpha", c_void_p),
+                ("grad_background", c_void_p), ("grad_camera", c_void_p)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("points_per_block", c_int32), ("item_entries", c_int32)]
 
@@ -63,9 +69,9 @@ def lib():
         L.trips_buffer_sizes.argtypes = [P(Config), P(Camera), c_int32, c_int64, P(Tuning),
                                          P(c_size_t), P(c_size_t)]
         L.trips_forward.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_void_p,
-                                    c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]
+                                    c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]
         L.trips_backward.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_void_p,
-                                     c_void_p, c_size_t, c_void_p, c_size_t] + [c_void_p] * 7
+                                     c_void_p, c_size_t, c_void_p, c_size_t] + [c_void_p] * 8
         L.trips_export_fragments.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
                                              c_size_t, c_void_p, c_void_p, c_void_p]
         L.trips_forward_stats.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
@@ -87,7 +93,7 @@ def lib():
         L.trips_autotune.restype = c_int32
         L.trips_plan_create.argtypes = ([P(Config), P(Points), P(Camera), c_int32, P(Tuning),
                                          c_void_p, c_void_p, c_size_t, c_void_p, c_size_t]
-                                        + [c_void_p] * 8 + [P(c_void_p)])
+                                        + [c_void_p] * 9 + [P(c_void_p)])
         L.trips_plan_launch.argtypes = [c_void_p, c_int32, c_void_p]
         L.trips_plan_destroy.argtypes = [c_void_p]
         for name in ("trips_layer_layout", "trips_buffer_sizes", "trips_forward", "trips_backward",
@@ -140,6 +146,19 @@ def layer_layout(cam, num_layers):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _extras(background=None, alpha_out=None, grad_alpha=None, grad_background=None,
+            grad_camera=None):
+    """A pointer to a trips_extras struct, or NULL when no field is given."""
+    fields = (background, alpha_out, grad_alpha, grad_background, grad_camera)
+    if all(f is None for f in fields):
+        return None, ctypes.c_void_p(0)
+    for f in fields:
+        if f is not None and (f.dtype != torch.float32 or not f.is_contiguous()):
+            raise ValueError("extra arrays must be contiguous float32")
+    e = Extras(*[f.data_ptr() if f is not None else None for f in fields])
+    return e, ctypes.c_void_p(ctypes.addressof(e))
 
 
 def _stream():
@@ -202,30 +221,52 @@ class Renderer:
         return Points(x.data_ptr(), y.data_ptr(), z.data_ptr(), sw.data_ptr(), alpha.data_ptr(),
                       desc.data_ptr(), self.n)
 
-    def forward(self, x, y, z, sw, alpha, desc, out=None):
-        """Flat float32 pyramid: views, then layers, each row-major [H_L][W_L][D]."""
+    def _texel_array(self, t, per_texel, name):
+        if t is not None and t.numel() != self.texels * per_texel:
+            raise ValueError("%s must hold %d values per texel" % (name, per_texel))
+
+    def forward(self, x, y, z, sw, alpha, desc, out=None, background=None, alpha_out=None):
+        """Flat float32 pyramid: views, then layers, each row-major [H_L][W_L][D].
+
+        background (optional, [P*D]): composited behind the kept fragments with the
+        transmittance they leave; alpha_out (optional, [P]) receives the coverage."""
         pts = self._points(x, y, z, sw, alpha, desc)
         if out is None:
             out = torch.empty(self.pyramid_numel(), dtype=torch.float32, device=self.device)
+        self._texel_array(background, self.D, "background")
+        self._texel_array(alpha_out, 1, "alpha_out")
+        keep, ext = _extras(background=background, alpha_out=alpha_out)
         _check(lib().trips_forward(ctypes.byref(self.cfg), ctypes.byref(pts), self.cams, self.V,
                                    ctypes.byref(self.tune), _ptr(out), _ptr(self.saved),
-                                   self.saved_bytes, _ptr(self.workspace), self.ws_bytes, _stream()),
+                                   self.saved_bytes, _ptr(self.workspace), self.ws_bytes, ext,
+                                   _stream()),
                "trips_forward")
         return out
 
-    def backward(self, x, y, z, sw, alpha, desc, grad_pyramid, outs=None):
-        """Gradients (x, y, z, sw, alpha, desc) of sum(grad_pyramid * pyramid)."""
+    def backward(self, x, y, z, sw, alpha, desc, grad_pyramid, outs=None, background=None,
+                 grad_alpha=None, grad_background=None, grad_camera=None):
+        """Gradients (x, y, z, sw, alpha, desc) of sum(grad_pyramid * pyramid)
+        (+ sum(grad_alpha * coverage) when grad_alpha is given).  background must be the one
+        the forward call used; grad_background ([P*D]) and grad_camera ([V, 16]: dR
+        row-major, dt, dfx, dfy, dcx, dcy per view) are filled when given."""
         pts = self._points(x, y, z, sw, alpha, desc)
         g = grad_pyramid.contiguous()
         if g.numel() != self.pyramid_numel() or g.dtype != torch.float32:
             raise ValueError("grad_pyramid must be float32 with the pyramid's size")
+        self._texel_array(background, self.D, "background")
+        self._texel_array(grad_alpha, 1, "grad_alpha")
+        self._texel_array(grad_background, self.D, "grad_background")
+        if grad_camera is not None and grad_camera.numel() != self.V * 16:
+            raise ValueError("grad_camera must hold 16 values per view")
         if outs is None:
             outs = [torch.empty(self.n, dtype=torch.float32, device=self.device) for _ in range(5)]
             outs.append(torch.empty((self.n, self.D), dtype=torch.float32, device=self.device))
+        keep, ext = _extras(background=background, grad_alpha=grad_alpha,
+                            grad_background=grad_background, grad_camera=grad_camera)
         _check(lib().trips_backward(ctypes.byref(self.cfg), ctypes.byref(pts), self.cams, self.V,
                                     ctypes.byref(self.tune), _ptr(g), _ptr(self.saved),
                                     self.saved_bytes, _ptr(self.workspace), self.ws_bytes,
-                                    *[_ptr(o) for o in outs], _stream()),
+                                    *[_ptr(o) for o in outs], ext, _stream()),
                "trips_backward")
         return outs
 
@@ -292,10 +333,11 @@ class Plan:
     """The batched form captured in a HIP graph: buffers bound once, replayed per launch."""
 
     def __init__(self, renderer, x, y, z, sw, alpha, desc, pyramid, grad_pyramid=None,
-                 grads=None):
+                 grads=None, **extras):
         r = renderer
         self.r = r
-        self.keep = (x, y, z, sw, alpha, desc, pyramid, grad_pyramid, grads)
+        self.keep = (x, y, z, sw, alpha, desc, pyramid, grad_pyramid, grads, extras)
+        self._ext_struct, ext = _extras(**extras)
         pts = r._points(x, y, z, sw, alpha, desc)
         g = grads if grads is not None else [None] * 6
         h = c_void_p()
@@ -305,7 +347,7 @@ class Plan:
         st = lib().trips_plan_create(ctypes.byref(r.cfg), ctypes.byref(pts), r.cams, r.V,
                                      ctypes.byref(r.tune), _ptr(pyramid), _ptr(r.saved),
                                      r.saved_bytes, _ptr(r.workspace), r.ws_bytes,
-                                     _ptr(grad_pyramid), *[_ptr(t) for t in g],
+                                     _ptr(grad_pyramid), *[_ptr(t) for t in g], ext,
                                      ctypes.c_void_p(cap.cuda_stream), ctypes.byref(h))
         if st != 0:
             raise TripsError(st, "trips_plan_create (hip error %d)" % lib().trips_last_hip_error())

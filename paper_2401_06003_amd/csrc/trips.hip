@@ -597,6 +597,39 @@ __device__ __forceinline__ uint32_t entry_corners(const Entry& e, const BinInfo&
   return mask;
 }
 
+// Optional inputs and outputs around the blend (any may be null): a background composited
+// behind the kept fragments, C += T_K bg with T_K the transmittance left after them; the
+// coverage 1 - T_K of every texel; in the backward pass the upstream gradient of the
+// coverage, the gradient of the background (T_K G) and the camera gradient.
+struct Extras {
+  float* alpha;               // [P]
+  const float* bg;            // [P][D], 16-byte aligned
+  const float* galpha;        // [P]
+  float* gbg;                 // [P][D], 16-byte aligned
+  float* gcam;                // [V][16]
+};
+
+// Write the composited colour and the coverage of texel `tex` (pyramid texel index).
+template <int D>
+__device__ __forceinline__ void write_texel(float (&C)[D], float T, size_t tex, float* __restrict__ pyr,
+                                            const float* __restrict__ bg, float* __restrict__ alpha) {
+  if (bg) {
+    const float4* bp = reinterpret_cast<const float4*>(bg + tex * D);
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q) {
+      const float4 bv = bp[q];
+      C[4 * q + 0] += T * bv.x;
+      C[4 * q + 1] += T * bv.y;
+      C[4 * q + 2] += T * bv.z;
+      C[4 * q + 3] += T * bv.w;
+    }
+  }
+  float4* op = reinterpret_cast<float4*>(pyr + tex * D);
+#pragma unroll
+  for (int q = 0; q < D / 4; ++q) op[q] = make_float4(C[4 * q], C[4 * q + 1], C[4 * q + 2], C[4 * q + 3]);
+  if (alpha) alpha[tex] = 1.0f - T;
+}
+
 // Blend the kept fragments of one texel front to back (Eq. 6-7) and write its outputs.
 template <int D>
 __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& bi, uint32_t b,
@@ -604,6 +637,7 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
                                                uint32_t n, const float* __restrict__ desc,
                                                float* __restrict__ pyr, uint32_t* __restrict__ npix,
                                                uint64_t* __restrict__ kkey, float* __restrict__ kgam,
+                                               const float* __restrict__ bg, float* __restrict__ alpha,
                                                int t) {
   const int lth = 8 - P.ltw;
   const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
@@ -642,12 +676,8 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
       }
     }
   }
-  if (i < bi.WL && j < bi.HL) {
-    const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
-    float4* op = reinterpret_cast<float4*>(pyr + o);
-#pragma unroll
-    for (int q = 0; q < D / 4; ++q) op[q] = make_float4(C[4 * q], C[4 * q + 1], C[4 * q + 2], C[4 * q + 3]);
-  }
+  if (i < bi.WL && j < bi.HL)
+    write_texel<D>(C, T, size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i, pyr, bg, alpha);
   npix[size_t(b) * TP + t] = n;
 #pragma unroll
   for (int m = 0; m < KEEP; ++m)
@@ -734,7 +764,8 @@ __global__ __launch_bounds__(256) void k_fwd_items(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
     const Entry* __restrict__ ent, const float* __restrict__ desc, float* __restrict__ pyr,
     uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam,
-    uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey, float* __restrict__ pgam) {
+    uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey, float* __restrict__ pgam,
+    const float* __restrict__ bg, float* __restrict__ alpha) {
   __shared__ uint32_t hist[TP];    // sorted fragments per texel in this round, then run starts
   __shared__ uint32_t tally[TP];   // all fragments per texel in this item
   __shared__ uint64_t thr[TP];     // current 16th key per texel
@@ -825,7 +856,7 @@ __global__ __launch_bounds__(256) void k_fwd_items(
   }
   const uint32_t n = tally[t];
   if (!multi) {
-    finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam, t);
+    finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam, bg, alpha, t);
   } else {
     // partial list of this texel: 16 keys and gammas stored contiguously (unused slots hold
     // KEY_NONE), read back as whole lists by the merge
@@ -857,7 +888,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_fwd_fine(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
     Entry* __restrict__ ent, const float* __restrict__ desc, float* __restrict__ pyr,
-    uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
+    uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam,
+    const float* __restrict__ bg, float* __restrict__ alpha) {
   constexpr int NF = 4 * FINE_E;     // fragment capacity
   __shared__ uint32_t hist[TP];      // fragments per texel, then the start of its run
   __shared__ uint32_t ws[4];
@@ -974,12 +1006,8 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
         kkey[(size_t(b) * KEEP + m) * TP + t] = kq;
         kgam[(size_t(b) * KEEP + m) * TP + t] = gq;
       }
-      if (i < bi.WL && j < bi.HL) {
-        const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
-        float4* op = reinterpret_cast<float4*>(pyr + o);
-#pragma unroll
-        for (int q = 0; q < D / 4; ++q) op[q] = make_float4(C[4 * q], C[4 * q + 1], C[4 * q + 2], C[4 * q + 3]);
-      }
+      if (i < bi.WL && j < bi.HL)
+        write_texel<D>(C, T, size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i, pyr, bg, alpha);
       npix[size_t(b) * TP + t] = cnt;
     }
   }
@@ -1002,7 +1030,8 @@ __global__ __launch_bounds__(256) void k_fwd_merge(
     const uint32_t* __restrict__ info, const uint32_t* __restrict__ pcnt,
     const uint64_t* __restrict__ pkey, const float* __restrict__ pgam,
     const float* __restrict__ desc, float* __restrict__ pyr, uint32_t* __restrict__ npix,
-    uint64_t* __restrict__ kkey, float* __restrict__ kgam) {
+    uint64_t* __restrict__ kkey, float* __restrict__ kgam, const float* __restrict__ bg,
+    float* __restrict__ alpha) {
   __shared__ uint64_t s_key[3][KEEP][64];
   __shared__ float s_gam[3][KEEP][64];
   __shared__ uint32_t s_n[3][64];
@@ -1057,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_fwd_merge(
         merge16(kk, kg, ok, og);
         n += s_n[q][lane];
       }
-      finalize_texel<D>(P, decode_bin(P, b), b, kk, kg, n, desc, pyr, npix, kkey, kgam, t);
+      finalize_texel<D>(P, decode_bin(P, b), b, kk, kg, n, desc, pyr, npix, kkey, kgam, bg, alpha, t);
     }
     __syncthreads();  // LDS is reused by the next unit
   }
@@ -1092,6 +1121,14 @@ __device__ __forceinline__ float dot_g(const float (&G)[D], const float4 (&tv)[D
   return acc;
 }
 
+// dst[0..D) = s * G (16-byte aligned).
+template <int D>
+__device__ __forceinline__ void write_scaled(float* dst, float s, const float (&G)[D]) {
+  float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+  for (int q = 0; q < D / 4; ++q) d4[q] = make_float4(s * G[4 * q], s * G[4 * q + 1], s * G[4 * q + 2], s * G[4 * q + 3]);
+}
+
 // One step of the reverse blend recurrence for kept fragment m (B holds B_m on entry and
 // B_{m-1} on return): returns (dL/dgamma_m, T_m gamma_m).
 __device__ __forceinline__ float2 blend_adjoint_step(float Tm, float gam, float gm, float& B) {
@@ -1111,23 +1148,31 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
                                                     const float* __restrict__ kgam,
                                                     const float* __restrict__ desc,
                                                     const float* __restrict__ gpyr,
-                                                    float2* __restrict__ bst) {
+                                                    float2* __restrict__ bst, const Extras X) {
   const int t = threadIdx.x;
   const uint32_t b = coarse_bins[blockIdx.x];  // in bounds (grid = bin count); used if valid
   if (blockIdx.x >= info[5]) return;
   const uint32_t n = npix[size_t(b) * TP + t];
-  if (n == 0) return;
+  if (n == 0 && !X.gbg) return;
   const BinInfo bi = decode_bin(P, b);
   const int lth = 8 - P.ltw;
   const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
   const int j = (bi.ty << lth) + (t >> P.ltw);
-  const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+  if (!(i < bi.WL && j < bi.HL)) return;  // (such texels hold no fragments)
+  const size_t tex = size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i;
+  const size_t o = tex * D;
   float G[D];
   const float4* gp = reinterpret_cast<const float4*>(gpyr + o);
 #pragma unroll
   for (int q = 0; q < D / 4; ++q) {
     float4 gv = gp[q];
     G[4 * q] = gv.x; G[4 * q + 1] = gv.y; G[4 * q + 2] = gv.z; G[4 * q + 3] = gv.w;
+  }
+  if (n == 0) {  // only the background shows
+    float4* gb = reinterpret_cast<float4*>(X.gbg + o);
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q) gb[q] = make_float4(G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]);
+    return;
   }
   const uint32_t k = min(n, uint32_t(KEEP));
   float gam[KEEP], Tm[KEEP], gm[KEEP];
@@ -1160,10 +1205,16 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
 #pragma unroll
     for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
   }
-  float B = 0.0f;
+  if (X.galpha) {  // the coverage blends a constant 1 through the same weights
+    const float ga = X.galpha[tex];
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) gm[m] += ga;
+  }
+  float B = X.bg ? dot_g<D>(G, *reinterpret_cast<const float4(*)[D / 4]>(X.bg + o)) : 0.0f;
 #pragma unroll
   for (int m = KEEP - 1; m >= 0; --m)
     if (uint32_t(m) < k) bst[(size_t(b) * KEEP + m) * TP + t] = blend_adjoint_step(Tm[m], gam[m], gm[m], B);
+  if (X.gbg) write_scaled<D>(X.gbg + o, T, G);
 }
 
 // bwd_items: per work item, each entry finds its corners in the tile's kept lists and writes
@@ -1305,7 +1356,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_bwd_fine(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
     const Entry* __restrict__ ent, const uint32_t* __restrict__ npix,
-    const float* __restrict__ desc, const float* __restrict__ gpyr, float* __restrict__ rows) {
+    const float* __restrict__ desc, const float* __restrict__ gpyr, float* __restrict__ rows,
+    const Extras X) {
   constexpr int RW = 4 + D;
   constexpr int NF = 4 * FINE_E;  // at most one kept fragment per fragment
   __shared__ float s_G[TP][D + 1];
@@ -1324,15 +1376,15 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
   Entry en = {};
   if (has) en = ent[e0 + t];
   const uint32_t k = min(npix[size_t(b) * TP + t], uint32_t(KEEP));
-  {  // upstream gradient of the tile's texels inside the layer
-    const int lth = 8 - P.ltw;
-    const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
-    const int j = (bi.ty << lth) + (t >> P.ltw);
-    if (i < bi.WL && j < bi.HL) {
-      const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
+  // upstream gradient of the tile's texels inside the layer
+  const int lth = 8 - P.ltw;
+  const int ti = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int tj = (bi.ty << lth) + (t >> P.ltw);
+  const bool inl = ti < bi.WL && tj < bi.HL;
+  const size_t tex = size_t(P.view[bi.v].lout[bi.L]) + size_t(tj) * bi.WL + ti;
+  if (inl) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
-    }
+    for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[tex * D + d];
   }
   float4 dv[D / 4];
 #pragma unroll
@@ -1362,24 +1414,28 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
     }
   }
   __syncthreads();
-  if (k > 0) {  // blend adjoint of texel t
+  if (inl && (k > 0 || X.gbg)) {  // blend adjoint of texel t (as in bwd_pixels)
     const uint32_t o0 = s_off[t];
     float G[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) G[d] = s_G[t][d];
+    const float ga = X.galpha ? X.galpha[tex] : 0.0f;
     float T = 1.0f;
     for (uint32_t m = 0; m < k; ++m) {  // front to back: T_m and g_m
       float4 tv[D / 4];
 #pragma unroll
       for (int r4 = 0; r4 < D / 4; ++r4) tv[r4] = s_desc[s_ent[o0 + m]][r4];
-      s_bst[o0 + m] = make_float2(dot_g<D>(G, tv), T);
+      float gm = dot_g<D>(G, tv);
+      if (X.galpha) gm += ga;
+      s_bst[o0 + m] = make_float2(gm, T);
       T = T * (1.0f - s_gam[o0 + m]);
     }
-    float B = 0.0f;
+    float B = X.bg ? dot_g<D>(G, *reinterpret_cast<const float4(*)[D / 4]>(X.bg + tex * D)) : 0.0f;
     for (uint32_t m = k; m-- > 0;) {  // back to front
       const float2 gt = s_bst[o0 + m];
       s_bst[o0 + m] = blend_adjoint_step(gt.y, s_gam[o0 + m], gt.x, B);
     }
+    if (X.gbg) write_scaled<D>(X.gbg + tex * D, T, G);
   }
   __syncthreads();
   if (!has) return;
@@ -1410,19 +1466,32 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
     r4[1 + q] = make_float4(tau[4 * q], tau[4 * q + 1], tau[4 * q + 2], tau[4 * q + 3]);
 }
 
+// Sum of v over the 64 lanes of a wavefront (a fixed butterfly, so the order never changes).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // bwd_points: per point, every view: read the rows of its entries, apply the layer and
-// footprint factors, then the chain rule through the projection; sum over views.
-template <int D>
+// footprint factors, then the chain rule through the projection; sum over views.  With CAM,
+// the workgroup also sums, per view, the gradient of the camera over its 256 points:
+// d/dR (row-major, X_c = R X_w + t), d/dt, d/dfx, d/dfy, d/dcx, d/dcy, written to
+// campart[block][view][16] for k_cam_reduce.
+template <int D, bool CAM>
 __global__ __launch_bounds__(256) void k_bwd_points(
     const Params P, const float* __restrict__ X, const float* __restrict__ Y,
     const float* __restrict__ Z, const float* __restrict__ SW, const float* __restrict__ A,
     const float* __restrict__ rows, float* __restrict__ gX, float* __restrict__ gY,
     float* __restrict__ gZ, float* __restrict__ gSW, float* __restrict__ gA,
-    float* __restrict__ gD) {
+    float* __restrict__ gD, float* __restrict__ campart) {
   constexpr int RW = 4 + D;
+  __shared__ float s_cam[CAM ? 4 : 1][16];
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= P.n) return;
-  const float x = X[p], y = Y[p], z = Z[p], sw = SW[p], alpha = A[p];
+  const bool live = p < P.n;
+  if (!CAM && !live) return;
+  float x = 0.f, y = 0.f, z = 0.f, sw = 0.f, alpha = 0.f;
+  if (live) { x = X[p]; y = Y[p]; z = Z[p]; sw = SW[p]; alpha = A[p]; }
   float ax = 0.f, ay = 0.f, az = 0.f, asw = 0.f, aal = 0.f;
   float at[D];
 #pragma unroll
@@ -1430,60 +1499,111 @@ __global__ __launch_bounds__(256) void k_bwd_points(
   for (int v = 0; v < P.V; ++v) {
     const ViewP& c = P.view[v];
     Geo g;
-    if (!project(c, x, y, z, sw, P.nl, P.eps, g)) continue;
-    float gxs = 0.f, gys = 0.f, gs = 0.f, gal = 0.f;
-    float gt[D];
+    const bool vis = live && project(c, x, y, z, sw, P.nl, P.eps, g);
+    float gxs = 0.f, gys = 0.f, gs = 0.f;
+    float dXc = 0.f, dYc = 0.f, dZc = 0.f, iz = 0.f;
+    if (vis) {
+      float gal = 0.f;
+      float gt[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) gt[d] = 0.0f;
+      for (int d = 0; d < D; ++d) gt[d] = 0.0f;
 #pragma unroll
-    for (int sel = 0; sel < 2; ++sel) {
-      if (sel >= g.nl) break;
-      const int L = g.L0 + sel;
-      const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
-      Foot ft;
-      if (!footprint(g.x, g.y, L, WL, HL, ft)) continue;
-      uint32_t tm[4];
-      touches(ft, P.ltw, tm);
-      float sA = 0.f, sBx = 0.f, sBy = 0.f;
+      for (int sel = 0; sel < 2; ++sel) {
+        if (sel >= g.nl) break;
+        const int L = g.L0 + sel;
+        const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
+        Foot ft;
+        if (!footprint(g.x, g.y, L, WL, HL, ft)) continue;
+        uint32_t tm[4];
+        touches(ft, P.ltw, tm);
+        float sA = 0.f, sBx = 0.f, sBy = 0.f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!tm[q]) continue;
-        const float4* r4 = reinterpret_cast<const float4*>(
-            rows + ((size_t(v) * NSLOT + sel * 4 + q) * size_t(P.n) + p) * RW);
-        const float4 h = r4[0];
-        sA += h.x; sBx += h.y; sBy += h.z;
+        for (int q = 0; q < 4; ++q) {
+          if (!tm[q]) continue;
+          const float4* r4 = reinterpret_cast<const float4*>(
+              rows + ((size_t(v) * NSLOT + sel * 4 + q) * size_t(P.n) + p) * RW);
+          const float4 h = r4[0];
+          sA += h.x; sBx += h.y; sBy += h.z;
 #pragma unroll
-        for (int qq = 0; qq < D / 4; ++qq) {
-          const float4 tv = r4[1 + qq];
-          gt[4 * qq] += tv.x; gt[4 * qq + 1] += tv.y; gt[4 * qq + 2] += tv.z; gt[4 * qq + 3] += tv.w;
+          for (int qq = 0; qq < D / 4; ++qq) {
+            const float4 tv = r4[1 + qq];
+            gt[4 * qq] += tv.x; gt[4 * qq + 1] += tv.y; gt[4 * qq + 2] += tv.z; gt[4 * qq + 3] += tv.w;
+          }
         }
+        const float io = g.io[sel];
+        const float sc = pow2i(-L);
+        gal += sA * io;
+        gs += sA * alpha * g.dio[sel];
+        gxs += sBx * io * alpha * sc;
+        gys += sBy * io * alpha * sc;
       }
-      const float io = g.io[sel];
-      const float sc = pow2i(-L);
-      gal += sA * io;
-      gs += sA * alpha * g.dio[sel];
-      gxs += sBx * io * alpha * sc;
-      gys += sBy * io * alpha * sc;
-    }
-    // chain rule: x = fx Xc/Zc + cx, y = fy Yc/Zc + cy, s = fx sw / Zc
-    const float iz = 1.0f / g.zc;
-    const float dXc = gxs * c.fx * iz;
-    const float dYc = gys * c.fy * iz;
-    const float dZc = -(gxs * c.fx * g.qx + gys * c.fy * g.qy + gs * g.s) * iz;
-    ax += c.R[0] * dXc + c.R[3] * dYc + c.R[6] * dZc;
-    ay += c.R[1] * dXc + c.R[4] * dYc + c.R[7] * dZc;
-    az += c.R[2] * dXc + c.R[5] * dYc + c.R[8] * dZc;
-    asw += gs * c.fx * iz;
-    // per-view sums first, then across views, so a batched call equals the sum of
-    // single-view calls bit for bit
-    aal += gal;
+      // chain rule: x = fx Xc/Zc + cx, y = fy Yc/Zc + cy, s = fx sw / Zc
+      iz = 1.0f / g.zc;
+      dXc = gxs * c.fx * iz;
+      dYc = gys * c.fy * iz;
+      dZc = -(gxs * c.fx * g.qx + gys * c.fy * g.qy + gs * g.s) * iz;
+      ax += c.R[0] * dXc + c.R[3] * dYc + c.R[6] * dZc;
+      ay += c.R[1] * dXc + c.R[4] * dYc + c.R[7] * dZc;
+      az += c.R[2] * dXc + c.R[5] * dYc + c.R[8] * dZc;
+      asw += gs * c.fx * iz;
+      // per-view sums first, then across views, so a batched call equals the sum of
+      // single-view calls bit for bit
+      aal += gal;
 #pragma unroll
-    for (int d = 0; d < D; ++d) at[d] += gt[d];
+      for (int d = 0; d < D; ++d) at[d] += gt[d];
+    }
+    if (CAM) {
+      float cv[16];
+      cv[0] = dXc * x; cv[1] = dXc * y; cv[2] = dXc * z;
+      cv[3] = dYc * x; cv[4] = dYc * y; cv[5] = dYc * z;
+      cv[6] = dZc * x; cv[7] = dZc * y; cv[8] = dZc * z;
+      cv[9] = dXc; cv[10] = dYc; cv[11] = dZc;
+      cv[12] = vis ? gxs * g.qx + gs * sw * iz : 0.0f;
+      cv[13] = vis ? gys * g.qy : 0.0f;
+      cv[14] = gxs; cv[15] = gys;
+      const int w = threadIdx.x >> 6;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const float r = wave_sum(cv[k]);
+        if ((threadIdx.x & 63) == 0) s_cam[w][k] = r;
+      }
+      __syncthreads();
+      if (threadIdx.x < 16)
+        campart[(size_t(blockIdx.x) * P.V + v) * 16 + threadIdx.x] =
+            ((s_cam[0][threadIdx.x] + s_cam[1][threadIdx.x]) + s_cam[2][threadIdx.x]) + s_cam[3][threadIdx.x];
+      __syncthreads();
+    }
   }
+  if (!live) return;
   gX[p] = ax; gY[p] = ay; gZ[p] = az; gSW[p] = asw; gA[p] = aal;
   float4* gd4 = reinterpret_cast<float4*>(gD + size_t(p) * D);
 #pragma unroll
   for (int q = 0; q < D / 4; ++q) gd4[q] = make_float4(at[4 * q], at[4 * q + 1], at[4 * q + 2], at[4 * q + 3]);
+}
+
+// cam_reduce: one workgroup per view sums the per-block camera partials in a fixed order.
+__global__ __launch_bounds__(256) void k_cam_reduce(const float* __restrict__ campart,
+                                                    uint32_t nblk, int32_t V,
+                                                    float* __restrict__ gcam) {
+  __shared__ float s_cam[4][16];
+  const int v = blockIdx.x;
+  float acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0f;
+  for (uint32_t bk = threadIdx.x; bk < nblk; bk += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] += campart[(size_t(bk) * V + v) * 16 + k];
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float r = wave_sum(acc[k]);
+    if ((threadIdx.x & 63) == 0) s_cam[w][k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16)
+    gcam[size_t(v) * 16 + threadIdx.x] =
+        ((s_cam[0][threadIdx.x] + s_cam[1][threadIdx.x]) + s_cam[2][threadIdx.x]) + s_cam[3][threadIdx.x];
 }
 
 // ------------------------------------------------------------------------------------
@@ -1547,7 +1667,7 @@ struct Layout {
       s_tables_end, s_work, s_ent;
   size_t saved_bytes;
   // workspace
-  size_t w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, ws_bytes;
+  size_t w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, ws_bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1656,6 +1776,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   o = scratch;
   lay.w_bst = take(NB * TP * KEEP * sizeof(float2));
   lay.w_rows = take(size_t(views) * NSLOT * size_t(n) * (4 + P.D) * 4);
+  lay.w_cam = take(size_t((n + 255) / 256) * size_t(views) * 16 * 4);
   lay.ws_bytes = std::max(fwd_end, o);
   return TRIPS_OK;
 }
@@ -1669,6 +1790,22 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// The optional arguments of one call; only the fields of its direction are taken.
+trips_status take_extras(const trips_extras* e, bool forward, bool backward, Extras& X) {
+  X = Extras{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (!e) return TRIPS_OK;
+  if (e->background && !aligned16(e->background)) return TRIPS_ERR_INVALID_ARG;
+  X.bg = e->background;
+  if (forward) X.alpha = e->alpha_out;
+  if (backward) {
+    if (e->grad_background && !aligned16(e->grad_background)) return TRIPS_ERR_INVALID_ARG;
+    X.galpha = e->grad_alpha;
+    X.gbg = e->grad_background;
+    X.gcam = e->grad_camera;
+  }
+  return TRIPS_OK;
+}
+
 trips_status check_points(const trips_points* pts, const Layout& lay) {
   if (!pts) return TRIPS_ERR_INVALID_ARG;
   if (pts->n != lay.P.n) return TRIPS_ERR_INVALID_ARG;
@@ -1680,7 +1817,7 @@ trips_status check_points(const trips_points* pts, const Layout& lay) {
 
 template <int D>
 trips_status launch_forward(const Layout& lay, const trips_points& pts, float* pyr, char* sv,
-                            char* ws, hipStream_t st) {
+                            char* ws, const Extras& X, hipStream_t st) {
   const Params& P = lay.P;
   uint32_t* H = reinterpret_cast<uint32_t*>(ws + lay.w_H);
   uint32_t* tot = reinterpret_cast<uint32_t*>(ws + lay.w_tot);
@@ -1741,19 +1878,19 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   {  // one workgroup per work item; workgroups beyond the item count exit at once
     StageTimer tm(ST_FWD_ITEMS, st);
     hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info, work,
-                       ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam);
+                       ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam, X.bg, X.alpha);
   }
   TRIPS_HIP(hipGetLastError());
   {  // one workgroup per fine tile; workgroups beyond their count exit at once
     StageTimer tm(ST_FWD_FINE, st);
     hipLaunchKernelGGL(k_fwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent,
-                       pts.desc, pyr, npix, kkey, kgam);
+                       pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
   }
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_FWD_MERGE, st);
     hipLaunchKernelGGL(k_fwd_merge<D>, dim3(1024), dim3(256), 0, st, P, item_start, multi_bins,
-                       info, pcnt, pkey, pgam, pts.desc, pyr, npix, kkey, kgam);
+                       info, pcnt, pkey, pgam, pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
   }
   TRIPS_HIP(hipGetLastError());
   return TRIPS_OK;
@@ -1762,7 +1899,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
 template <int D>
 trips_status launch_backward(const Layout& lay, const trips_points& pts, const float* gpyr,
                              const char* sv, char* ws, float* gx, float* gy, float* gz, float* gsw,
-                             float* ga, float* gd, hipStream_t st) {
+                             float* ga, float* gd, const Extras& X, hipStream_t st) {
   const Params& P = lay.P;
   float2* bst = reinterpret_cast<float2*>(ws + lay.w_bst);
   float* rows = reinterpret_cast<float*>(ws + lay.w_rows);
@@ -1778,7 +1915,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   {
     StageTimer tm(ST_BWD_PIXELS, st);
     hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
-                       kkey, kgam, pts.desc, gpyr, bst);
+                       kkey, kgam, pts.desc, gpyr, bst, X);
   }
   TRIPS_HIP(hipGetLastError());
   {
@@ -1790,15 +1927,32 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   {
     StageTimer tm(ST_BWD_FINE, st);
     hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent, npix,
-                       pts.desc, gpyr, rows);
+                       pts.desc, gpyr, rows, X);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.n > 0) {
     StageTimer tm(ST_BWD_POINTS, st);
-    hipLaunchKernelGGL(k_bwd_points<D>, dim3(uint32_t((P.n + 255) / 256)), dim3(256), 0, st, P,
-                       pts.x, pts.y, pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd);
+    const uint32_t nblk = uint32_t((P.n + 255) / 256);
+    float* campart = reinterpret_cast<float*>(ws + lay.w_cam);
+    if (X.gcam)
+      hipLaunchKernelGGL((k_bwd_points<D, true>), dim3(nblk), dim3(256), 0, st, P, pts.x, pts.y,
+                         pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, campart);
+    else
+      hipLaunchKernelGGL((k_bwd_points<D, false>), dim3(nblk), dim3(256), 0, st, P, pts.x, pts.y,
+                         pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, campart);
   }
   TRIPS_HIP(hipGetLastError());
+  if (X.gcam) {
+    if (P.n > 0) {
+      hipLaunchKernelGGL(k_cam_reduce, dim3(uint32_t(P.V)), dim3(256), 0, st,
+                         reinterpret_cast<const float*>(ws + lay.w_cam),
+                         uint32_t((P.n + 255) / 256), int32_t(P.V), X.gcam);
+    } else {
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(X.gcam),
+                         uint32_t(P.V * 16), 0u);
+    }
+    TRIPS_HIP(hipGetLastError());
+  }
   return TRIPS_OK;
 }
 
@@ -1817,6 +1971,7 @@ trips_status check_buffers(const Layout& lay, const void* saved, size_t saved_by
 
 struct trips_plan {
   Layout lay;
+  Extras xf, xb;  // optional arguments of the forward and the backward launches
   trips_points pts;
   float* pyr;
   void* saved;
@@ -1899,24 +2054,26 @@ trips_status trips_buffer_sizes(const trips_config* cfg, const trips_camera* cam
 trips_status trips_forward(const trips_config* cfg, const trips_points* pts,
                            const trips_camera* cams, int32_t views, const trips_tuning* tun,
                            float* pyr, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes,
-                           hipStream_t st) {
+                           const trips_extras* extras, hipStream_t st) {
   Layout lay;
   trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, tun, lay);
   if (s != TRIPS_OK) return s;
   if ((s = check_points(pts, lay)) != TRIPS_OK) return s;
   if ((s = check_buffers(lay, saved, saved_bytes, ws, ws_bytes, true)) != TRIPS_OK) return s;
   if (!pyr || !aligned16(pyr)) return TRIPS_ERR_INVALID_ARG;
+  Extras X;
+  if ((s = take_extras(extras, true, false, X)) != TRIPS_OK) return s;
   char* sv = static_cast<char*>(saved);
   char* w = static_cast<char*>(ws);
-  return cfg->desc_dim == 4 ? launch_forward<4>(lay, *pts, pyr, sv, w, st)
-                            : launch_forward<8>(lay, *pts, pyr, sv, w, st);
+  return cfg->desc_dim == 4 ? launch_forward<4>(lay, *pts, pyr, sv, w, X, st)
+                            : launch_forward<8>(lay, *pts, pyr, sv, w, X, st);
 }
 
 trips_status trips_backward(const trips_config* cfg, const trips_points* pts,
                             const trips_camera* cams, int32_t views, const trips_tuning* tun,
                             const float* gpyr, const void* saved, size_t saved_bytes, void* ws,
                             size_t ws_bytes, float* gx, float* gy, float* gz, float* gsw,
-                            float* ga, float* gd, hipStream_t st) {
+                            float* ga, float* gd, const trips_extras* extras, hipStream_t st) {
   Layout lay;
   trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, tun, lay);
   if (s != TRIPS_OK) return s;
@@ -1925,10 +2082,12 @@ trips_status trips_backward(const trips_config* cfg, const trips_points* pts,
   if (!gpyr || !aligned16(gpyr)) return TRIPS_ERR_INVALID_ARG;
   if (lay.P.n > 0 && (!gx || !gy || !gz || !gsw || !ga || !gd || !aligned16(gd)))
     return TRIPS_ERR_INVALID_ARG;
+  Extras X;
+  if ((s = take_extras(extras, false, true, X)) != TRIPS_OK) return s;
   const char* sv = static_cast<const char*>(saved);
   char* w = static_cast<char*>(ws);
-  return cfg->desc_dim == 4 ? launch_backward<4>(lay, *pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st)
-                            : launch_backward<8>(lay, *pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st);
+  return cfg->desc_dim == 4 ? launch_backward<4>(lay, *pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, X, st)
+                            : launch_backward<8>(lay, *pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, X, st);
 }
 
 trips_status trips_export_fragments(const trips_config* cfg, const trips_camera* cams,
@@ -2024,10 +2183,10 @@ trips_status trips_autotune(const trips_config* cfg, const trips_points* pts,
       hipError_t e = hipEventRecord(e0, st);
       if (e == hipSuccess) {
         rs = trips_forward(cfg, pts, cams, views, &candidates[c], pyr, saved, saved_bytes, ws,
-                           ws_bytes, st);
+                           ws_bytes, nullptr, st);
         if (rs == TRIPS_OK)
           rs = trips_backward(cfg, pts, cams, views, &candidates[c], gpyr, saved, saved_bytes, ws,
-                              ws_bytes, gx, gy, gz, gsw, ga, gd, st);
+                              ws_bytes, gx, gy, gz, gsw, ga, gd, nullptr, st);
         if (rs == TRIPS_OK) e = hipEventRecord(e1, st);
         if (rs == TRIPS_OK && e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -2049,8 +2208,8 @@ trips_status trips_plan_create(const trips_config* cfg, const trips_points* pts,
                                const trips_camera* cams, int32_t views, const trips_tuning* tun,
                                float* pyr, void* saved, size_t saved_bytes, void* ws,
                                size_t ws_bytes, const float* gpyr, float* gx, float* gy, float* gz,
-                               float* gsw, float* ga, float* gd, hipStream_t st,
-                               trips_plan** out) {
+                               float* gsw, float* ga, float* gd, const trips_extras* extras,
+                               hipStream_t st, trips_plan** out) {
   if (!out || !st) return TRIPS_ERR_INVALID_ARG;  // the null stream cannot be captured
   *out = nullptr;
   Layout lay;
@@ -2063,9 +2222,14 @@ trips_status trips_plan_create(const trips_config* cfg, const trips_points* pts,
   if (bwd && (!aligned16(gpyr) ||
               (lay.P.n > 0 && (!gx || !gy || !gz || !gsw || !ga || !gd || !aligned16(gd)))))
     return TRIPS_ERR_INVALID_ARG;
+  Extras xf, xb;
+  if ((s = take_extras(extras, true, false, xf)) != TRIPS_OK) return s;
+  if ((s = take_extras(extras, false, true, xb)) != TRIPS_OK) return s;
   trips_plan* pl = new (std::nothrow) trips_plan();
   if (!pl) return TRIPS_ERR_INVALID_ARG;
   pl->lay = lay;
+  pl->xf = xf;
+  pl->xb = xb;
   pl->pts = *pts;
   pl->pyr = pyr; pl->saved = saved; pl->ws = ws; pl->gpyr = gpyr;
   pl->gx = gx; pl->gy = gy; pl->gz = gz; pl->gsw = gsw; pl->ga = ga; pl->gd = gd;
@@ -2079,11 +2243,11 @@ trips_status trips_plan_create(const trips_config* cfg, const trips_points* pts,
     char* sv = static_cast<char*>(saved);
     char* w = static_cast<char*>(ws);
     if (which & 1)
-      ls = lay.P.D == 4 ? launch_forward<4>(lay, pl->pts, pyr, sv, w, st)
-                        : launch_forward<8>(lay, pl->pts, pyr, sv, w, st);
+      ls = lay.P.D == 4 ? launch_forward<4>(lay, pl->pts, pyr, sv, w, pl->xf, st)
+                        : launch_forward<8>(lay, pl->pts, pyr, sv, w, pl->xf, st);
     if (ls == TRIPS_OK && (which & 2))
-      ls = lay.P.D == 4 ? launch_backward<4>(lay, pl->pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st)
-                        : launch_backward<8>(lay, pl->pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, st);
+      ls = lay.P.D == 4 ? launch_backward<4>(lay, pl->pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, pl->xb, st)
+                        : launch_backward<8>(lay, pl->pts, gpyr, sv, w, gx, gy, gz, gsw, ga, gd, pl->xb, st);
     e = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;

@@ -90,19 +90,26 @@ def test_forward_validates_before_launch():
     f = L.trips_forward
     # null point arrays
     assert f(ctypes.byref(cfg), ctypes.byref(null_pts), cams, 1, None, fake, fake, sv.value, fake,
-             ws.value, None) == -1
+             ws.value, None, None) == -1
     # saved / workspace too small
     assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake, sv.value - 256, fake,
-             ws.value, None) == -2
+             ws.value, None, None) == -2
     assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake, sv.value, fake,
-             ws.value - 256, None) == -2
+             ws.value - 256, None, None) == -2
     # misaligned saved buffer
     assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake + 8, sv.value, fake,
-             ws.value, None) == -1
+             ws.value, None, None) == -1
+    # misaligned background (optional arguments are validated too)
+    ext = tp.Extras(fake + 4, None, None, None, None)
+    assert f(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake, sv.value, fake,
+             ws.value, ctypes.byref(ext), None) == -1
     # point count differs from the one the buffers were sized for is still validated per call
     b = L.trips_backward
     assert b(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, 0, fake, sv.value, fake, ws.value,
-             fake, fake, fake, fake, fake, fake, None) == -1   # null grad_pyramid
+             fake, fake, fake, fake, fake, fake, None, None) == -1   # null grad_pyramid
+    ext = tp.Extras(None, None, None, fake + 4, None)  # misaligned grad_background
+    assert b(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake, sv.value, fake,
+             ws.value, fake, fake, fake, fake, fake, fake, ctypes.byref(ext), None) == -1
     assert L.trips_status_string(-3) == b"problem exceeds 32-bit fragment indexing"
 
 

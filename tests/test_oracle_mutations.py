@@ -27,8 +27,8 @@ MUTATIONS = [
      "if (x->z != y->z) return x->z > y->z ? -1 : 1;"),
     ("index tie order reversed", "if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;",
      "if (x->idx != y->idx) return x->idx > y->idx ? -1 : 1;"),
-    ("transmittance not updated", "      T = T * (1.0 - f->gamma);\n    }\n    a = b;",
-     "    }\n    a = b;"),
+    ("transmittance not updated", "      T = T * (1.0 - f->gamma);\n    }\n    for (int d = 0; d < D; ++d) pyr",
+     "    }\n    for (int d = 0; d < D; ++d) pyr"),
     ("weight drops beta", "f->gamma = ((wx * wy) * p->iota[sel]) * alpha;",
      "f->gamma = p->iota[sel] * alpha;"),
     ("adjoint recurrence sign", "double dgam = Tm[m] * (gm - B);", "double dgam = Tm[m] * (gm + B);"),
@@ -38,9 +38,23 @@ MUTATIONS = [
     ("size gradient uses fy", "gSW[p] = gss[p] * fx / Zc;", "gSW[p] = gss[p] * fy * 1.5 / Zc;"),
     ("descriptor gradient misses T", "double w = Tm[m] * f->gamma;\n      for (int d = 0; d < D; ++d) gDESC",
      "double w = f->gamma;\n      for (int d = 0; d < D; ++d) gDESC"),
+    ("coverage is the transmittance", "if (alpha) alpha[pix] = 1.0 - T;", "if (alpha) alpha[pix] = T;"),
+    ("background not behind the list", "pyr[pix * D + d] = col[d] + (bg ? T * bg[pix * D + d] : 0.0);",
+     "pyr[pix * D + d] = col[d] + (bg ? bg[pix * D + d] : 0.0);"),
+    ("adjoint ignores the background", "      for (int d = 0; d < D; ++d) B += g[d] * bg[pix * D + d];",
+     "      for (int d = 0; d < D; ++d) B += 0.0 * bg[pix * D + d];"),
+    ("background gradient misses T", "for (int d = 0; d < D; ++d) gbg[pix * D + d] = T * g[d];",
+     "for (int d = 0; d < D; ++d) gbg[pix * D + d] = g[d];"),
+    ("coverage gradient dropped", "if (Galpha) gm += Galpha[pix];", "if (Galpha) gm += 0.0;"),
+    ("rotation gradient transposed", "gcam[3 * r + k] += dX[r] * Xw[k];", "gcam[3 * k + r] += dX[r] * Xw[k];"),
+    ("focal gradient drops size term", "gcam[12] += gxs[p] * q->Xc / Zc + gss[p] * sw / Zc;",
+     "gcam[12] += gxs[p] * q->Xc / Zc;"),
+    ("principal point gradient swapped", "gcam[14] += gxs[p];\n      gcam[15] += gys[p];",
+     "gcam[14] += gys[p];\n      gcam[15] += gxs[p];"),
 ]
 
-PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_backward.py"]
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_backward.py",
+             "tests/test_oracle_extras.py"]
 
 
 def _run_pins_with(lib_path):
