@@ -125,7 +125,8 @@ trips_status trips_buffer_sizes(const trips_config* cfg_host, const trips_camera
 /* Forward render (Eq. 1-7).  pyramid_out: float32, for each view in order, each layer
    in order, row-major [H_L][W_L][D]; overwritten.  `saved` receives the per-texel list
    lengths, the kept fragments (<= 16 per texel, front to back) and the tile entries,
-   which trips_backward and trips_export_fragments read. */
+   which trips_backward and trips_export_fragments read.  extras_host (may be NULL):
+   background (composited) and alpha_out (written), see trips_extras. */
 trips_status trips_forward(const trips_config* cfg_host, const trips_points* pts_host,
                            const trips_camera* cams_host, int32_t views,
                            const trips_tuning* tuning_host, float* pyramid_out, void* saved,
@@ -137,7 +138,9 @@ trips_status trips_forward(const trips_config* cfg_host, const trips_points* pts
    All six gradient outputs are device float32 arrays ([n], desc [n][D]) and are
    OVERWRITTEN (culled points get 0).  The per-texel blend state is recomputed from the
    kept fragments, not stored.  Sort order, culling and the 16-element clamp are
-   piecewise constant and carry no gradient. */
+   piecewise constant and carry no gradient.  extras_host (may be NULL): the background
+   the forward call used, grad_alpha (adds sum(grad_alpha * alpha_out) to the loss), and
+   the outputs grad_background and grad_camera, see trips_extras. */
 trips_status trips_backward(const trips_config* cfg_host, const trips_points* pts_host,
                             const trips_camera* cams_host, int32_t views,
                             const trips_tuning* tuning_host, const float* grad_pyramid,
@@ -210,7 +213,8 @@ trips_status trips_autotune(const trips_config* cfg_host, const trips_points* pt
    kernels for all views.  The plan owns only host objects (the graphs); all device
    memory still comes from the caller.  trips_plan_create captures on `stream`, which
    must be a created stream (not the null stream) with no capture in progress;
-   grad_pyramid may be NULL for a forward-only plan.  Launches may use any stream. */
+   grad_pyramid may be NULL for a forward-only plan.  The optional arguments (extras_host,
+   may be NULL) are bound at creation too.  Launches may use any stream. */
 typedef struct trips_plan trips_plan;
 
 trips_status trips_plan_create(const trips_config* cfg_host, const trips_points* pts_host,
