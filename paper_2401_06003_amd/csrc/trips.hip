@@ -377,122 +377,171 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
   const uint32_t b = blockIdx.x * 64 + lane;
   const uint32_t per = (nblk + CS_SEG - 1) / CS_SEG;
   const uint32_t k0 = min(nblk, seg * per), k1 = min(nblk, k0 + per);
+  // rows are read eight at a time (independent loads; rows past the segment read its last
+  // row, a valid address, and are not used)
+  constexpr uint32_t RB = 8;
   uint32_t sum = 0;
   if (b < NB)
-    for (uint32_t k = k0; k < k1; ++k) sum += H[size_t(k) * NB + b];
+    for (uint32_t k = k0; k < k1; k += RB) {
+      uint32_t v[RB];
+#pragma unroll
+      for (uint32_t q = 0; q < RB; ++q) v[q] = H[size_t(min(k + q, k1 - 1)) * NB + b];
+#pragma unroll
+      for (uint32_t q = 0; q < RB; ++q) sum += k + q < k1 ? v[q] : 0u;
+    }
   ssum[seg][lane] = sum;
   __syncthreads();
   uint32_t run = 0;
   for (uint32_t s = 0; s < seg; ++s) run += ssum[s][lane];
   if (b < NB) {
     if (seg == CS_SEG - 1) tot[b] = run + sum;
-    for (uint32_t k = k0; k < k1; ++k) {
-      size_t o = size_t(k) * NB + b;
-      uint32_t h = H[o];
-      H[o] = run;
-      run += h;
+    for (uint32_t k = k0; k < k1; k += RB) {
+      uint32_t v[RB];
+#pragma unroll
+      for (uint32_t q = 0; q < RB; ++q) v[q] = H[size_t(min(k + q, k1 - 1)) * NB + b];
+#pragma unroll
+      for (uint32_t q = 0; q < RB; ++q)
+        if (k + q < k1) {
+          H[size_t(k + q) * NB + b] = run;
+          run += v[q];
+        }
     }
   }
 }
 
-// binscan (one workgroup of 1024): bin_start = exclusive scan of totals; every bin is cut
-// into max(1, ceil(total / item_e)) work items; item_start = exclusive scan of those.
-// Bins with more than one item are listed in multi_bins (their partial lists are merged).
-__global__ __launch_bounds__(1024) void k_binscan(const uint32_t* __restrict__ tot,
-                                                  uint32_t* __restrict__ bin_start,
-                                                  uint32_t* __restrict__ item_start,
-                                                  uint32_t* __restrict__ multi_bins,
-                                                  uint4* __restrict__ fine_work,
-                                                  uint32_t* __restrict__ coarse_bins,
-                                                  uint32_t* __restrict__ info, uint32_t NB,
-                                                  uint32_t item_e) {
-  __shared__ uint4 ws[16];
-  __shared__ uint32_t s_bucket[NBUCKET];
-  if (threadIdx.x < NBUCKET) s_bucket[threadIdx.x] = 0;
-  uint32_t nb_own[NBUCKET];  // items of this thread's bins per size class
-#pragma unroll
-  for (int q = 0; q < NBUCKET; ++q) nb_own[q] = 0;
-  uint32_t carry_e = 0, carry_i = 0, carry_m = 0, carry_f = 0;
-  uint32_t nxt[4];  // the next chunk's counts, loaded one chunk ahead
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t idx = threadIdx.x * 4 + k;
-    nxt[k] = idx < NB ? tot[idx] : 0u;
+// The tile scan in three short passes over chunks of 64 tiles (one wavefront each).  A tile
+// of at most FINE_E entries is listed in fine_work; every other tile is listed in coarse_bins
+// and cut into ceil(total / item_e) work items; tiles with more than one item are listed in
+// multi_bins (their partial lists are merged).  bin_start and item_start are the exclusive
+// scans of entries and items.
+constexpr uint32_t CHUNK = 64;
+constexpr int CSUM = 4 + NBUCKET;  // per chunk: entries, items, multi tiles, fine tiles, classes
+
+// ceil(a / b) for b > 0: the correctly rounded double quotient of integers below 2^33 is
+// never rounded across an integer (a quotient just below k is at least 1/b below it), so its
+// ceiling is exact.
+__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) {
+  return uint32_t(ceil(double(a) / double(b)));
+}
+
+struct TileCount { uint32_t e, it, multi, fine; };
+__device__ __forceinline__ TileCount tile_count(const uint32_t* __restrict__ tot, uint32_t b,
+                                                uint32_t NB, uint32_t item_e) {
+  TileCount r{0u, 0u, 0u, 0u};
+  if (b < NB) {
+    r.e = tot[b];
+    r.fine = r.e <= FINE_E ? 1u : 0u;
+    r.it = r.fine ? 0u : ceil_div(r.e, item_e);
+    r.multi = r.it > 1 ? 1u : 0u;
   }
-  for (uint32_t base = 0; base < NB; base += 4096) {
-    // fine tiles get no work item (they are listed in fine_work); the others get one item
-    // per item_e entries
-    uint32_t e[4], it[4], se = 0, si = 0, sm = 0, sf = 0;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      e[k] = nxt[k];
-      const uint32_t nidx = base + 4096 + threadIdx.x * 4 + k;
-      nxt[k] = nidx < NB ? tot[nidx] : 0u;
-    }
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// chunksum: per chunk, the four sums and the items per size class.
+__global__ __launch_bounds__(64) void k_chunksum(const uint32_t* __restrict__ tot,
+                                                 uint32_t* __restrict__ csum, uint32_t NB,
+                                                 uint32_t item_e) {
+  const uint32_t b = blockIdx.x * CHUNK + threadIdx.x;
+  const TileCount c = tile_count(tot, b, NB, item_e);
+  // it - 1 items of item_e entries (class 0) and a last one of the rest
+  const uint32_t cls = c.it ? size_class(c.e - (c.it - 1) * item_e, item_e) : 0u;
+  uint32_t v[CSUM];
+  v[0] = c.e; v[1] = c.it; v[2] = c.multi; v[3] = c.fine;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      uint32_t idx = base + threadIdx.x * 4 + k;
-      const bool fine = idx < NB && e[k] <= FINE_E;
-      it[k] = (idx < NB && !fine) ? (e[k] + item_e - 1) / item_e : 0u;
-      se += e[k];
-      si += it[k];
-      sm += it[k] > 1 ? 1u : 0u;
-      sf += fine ? 1u : 0u;
-      if (it[k] > 0) {  // it - 1 items of item_e entries and a last one of the rest
-        const uint32_t last = e[k] - (it[k] - 1) * item_e;
+  for (int q = 0; q < NBUCKET; ++q)
+    v[4 + q] = (q == 0 && c.it ? c.it - 1 : 0u) + (c.it && cls == uint32_t(q) ? 1u : 0u);
 #pragma unroll
-        for (int q = 0; q < NBUCKET; ++q)
-          nb_own[q] += (q == 0 ? it[k] - 1 : 0u) + (q == size_class(last, item_e) ? 1u : 0u);
-      }
+  for (int q = 0; q < CSUM; ++q) {
+    const uint32_t w = wave_sum_u32(v[q]);
+    if (threadIdx.x == 0) csum[size_t(blockIdx.x) * CSUM + q] = w;
+  }
+}
+
+// chunkscan (one workgroup): exclusive scan of the chunk sums, the totals and the first work
+// slot of each size class.
+__global__ __launch_bounds__(1024) void k_chunkscan(const uint32_t* __restrict__ csum,
+                                                    uint32_t* __restrict__ coff,
+                                                    uint32_t* __restrict__ bin_start,
+                                                    uint32_t* __restrict__ item_start,
+                                                    uint32_t* __restrict__ info, uint32_t NB,
+                                                    uint32_t nchunks) {
+  __shared__ uint4 ws[16];
+  __shared__ uint32_t s_cls[NBUCKET];
+  if (threadIdx.x < NBUCKET) s_cls[threadIdx.x] = 0;
+  __syncthreads();
+  uint4 carry = make_uint4(0u, 0u, 0u, 0u);
+  uint32_t cls[NBUCKET];
+#pragma unroll
+  for (int q = 0; q < NBUCKET; ++q) cls[q] = 0;
+  for (uint32_t c0 = 0; c0 < nchunks; c0 += 1024) {
+    const uint32_t c = c0 + threadIdx.x;
+    uint4 x = make_uint4(0u, 0u, 0u, 0u);
+    if (c < nchunks) {
+      const uint32_t* r = csum + size_t(c) * CSUM;
+      x = make_uint4(r[0], r[1], r[2], r[3]);
+#pragma unroll
+      for (int q = 0; q < NBUCKET; ++q) cls[q] += r[4 + q];
     }
     uint4 t4;
-    const uint4 o4 = block_excl_scan4<16>(make_uint4(se, si, sm, sf), ws, t4);
-    uint32_t oe = o4.x, oi = o4.y, om = o4.z, of = o4.w;
-    const uint32_t te = t4.x, ti = t4.y, tm = t4.z, tf = t4.w;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      uint32_t idx = base + threadIdx.x * 4 + k;
-      if (idx < NB) {
-        bin_start[idx] = carry_e + oe;
-        item_start[idx] = carry_i + oi;
-        if (it[k] > 1) multi_bins[carry_m + om] = idx;
-        if (e[k] <= FINE_E)
-          fine_work[carry_f + of] = make_uint4(idx, carry_e + oe, carry_e + oe + e[k], 0u);
-        else
-          coarse_bins[idx - (carry_f + of)] = idx;  // tiles before idx that are not fine
-      }
-      oe += e[k];
-      oi += it[k];
-      om += it[k] > 1 ? 1u : 0u;
-      of += (idx < NB && e[k] <= FINE_E) ? 1u : 0u;
+    const uint4 o = block_excl_scan4<16>(x, ws, t4);
+    if (c < nchunks) {
+      uint32_t* w = coff + size_t(c) * 4;
+      w[0] = carry.x + o.x; w[1] = carry.y + o.y; w[2] = carry.z + o.z; w[3] = carry.w + o.w;
     }
-    carry_e += te;
-    carry_i += ti;
-    carry_m += tm;
-    carry_f += tf;
+    carry.x += t4.x; carry.y += t4.y; carry.z += t4.z; carry.w += t4.w;
   }
 #pragma unroll
   for (int q = 0; q < NBUCKET; ++q) {
-    const uint32_t w = wave_incl_scan(nb_own[q]);
-    if ((threadIdx.x & 63) == 63 && w) atomicAdd(&s_bucket[q], w);
+    const uint32_t w = wave_sum_u32(cls[q]);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(&s_cls[q], w);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    bin_start[NB] = carry_e;
-    item_start[NB] = carry_i;
-    info[0] = carry_e;
-    info[1] = carry_i;
+    bin_start[NB] = carry.x;
+    item_start[NB] = carry.y;
+    info[0] = carry.x;
+    info[1] = carry.y;
     info[2] = 0;  // visible (point, view) pairs, accumulated by the scatter pass
-    info[3] = carry_m;
-    info[4] = carry_f;
-    info[5] = NB - carry_f;
+    info[3] = carry.z;
+    info[4] = carry.w;
+    info[5] = NB - carry.w;
     uint32_t o = 0;
     for (int q = 0; q < NBUCKET; ++q) {  // first work slot of each size class; fill counters
       info[INFO_BUCKET + q] = o;
       info[INFO_BUCKET + NBUCKET + q] = 0;
-      o += s_bucket[q];
+      o += s_cls[q];
     }
   }
+}
+
+// binscan: per chunk (one wavefront), the tiles' starts and list entries.
+__global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot,
+                                                const uint32_t* __restrict__ coff,
+                                                uint32_t* __restrict__ bin_start,
+                                                uint32_t* __restrict__ item_start,
+                                                uint32_t* __restrict__ multi_bins,
+                                                uint4* __restrict__ fine_work,
+                                                uint32_t* __restrict__ coarse_bins, uint32_t NB,
+                                                uint32_t item_e) {
+  const uint32_t b = blockIdx.x * CHUNK + threadIdx.x;
+  const TileCount c = tile_count(tot, b, NB, item_e);
+  const uint32_t* co = coff + size_t(blockIdx.x) * 4;
+  const uint32_t oe = co[0] + wave_incl_scan(c.e) - c.e;
+  const uint32_t oi = co[1] + wave_incl_scan(c.it) - c.it;
+  const uint32_t om = co[2] + wave_incl_scan(c.multi) - c.multi;
+  const uint32_t of = co[3] + wave_incl_scan(c.fine) - c.fine;
+  if (b >= NB) return;
+  bin_start[b] = oe;
+  item_start[b] = oi;
+  if (c.multi) multi_bins[om] = b;
+  if (c.fine) fine_work[of] = make_uint4(b, oe, oe + c.e, 0u);
+  else coarse_bins[b - of] = b;  // tiles before b that are not fine
 }
 
 // scatter: the count pass again, with LDS ranks; entry -> bin_start + H (column prefix) + rank.
@@ -1667,7 +1716,7 @@ struct Layout {
       s_tables_end, s_work, s_ent;
   size_t saved_bytes;
   // workspace
-  size_t w_H, w_tot, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, ws_bytes;
+  size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, ws_bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1768,6 +1817,8 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   // forward scratch
   lay.w_H = take(size_t(P.nblk) * NB * 4);
   lay.w_tot = take(NB * 4);
+  lay.w_csum = take(((NB + CHUNK - 1) / CHUNK) * CSUM * 4);
+  lay.w_coff = take(((NB + CHUNK - 1) / CHUNK) * 4 * 4);
   lay.w_pcnt = take(size_t(lay.icap) * TP * 4);
   lay.w_pkey = take(size_t(lay.icap) * TP * KEEP * 8);
   lay.w_pgam = take(size_t(lay.icap) * TP * KEEP * 4);
@@ -1853,8 +1904,14 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BINSCAN, st);
-    hipLaunchKernelGGL(k_binscan, dim3(1), dim3(1024), 0, st, tot, bin_start, item_start,
-                       multi_bins, fine_work, coarse_bins, info, P.NB, P.item_e);
+    const uint32_t nch = (P.NB + CHUNK - 1) / CHUNK;
+    uint32_t* csum = reinterpret_cast<uint32_t*>(ws + lay.w_csum);
+    uint32_t* coff = reinterpret_cast<uint32_t*>(ws + lay.w_coff);
+    hipLaunchKernelGGL(k_chunksum, dim3(nch), dim3(CHUNK), 0, st, tot, csum, P.NB, P.item_e);
+    hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, st, csum, coff, bin_start, item_start,
+                       info, P.NB, nch);
+    hipLaunchKernelGGL(k_binscan, dim3(nch), dim3(CHUNK), 0, st, tot, coff, bin_start, item_start,
+                       multi_bins, fine_work, coarse_bins, P.NB, P.item_e);
   }
   TRIPS_HIP(hipGetLastError());
   {
