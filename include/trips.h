@@ -186,7 +186,7 @@ int32_t trips_last_hip_error(void);
    milliseconds and the number of launches since the last read (or enable), then resets.
    Stage k is named by trips_stage_name(k), k < TRIPS_NUM_STAGES.  The events are host
    objects owned by the library; no device memory is allocated. */
-#define TRIPS_NUM_STAGES 13
+#define TRIPS_NUM_STAGES 12
 trips_status trips_timing_enable(int32_t enable);
 trips_status trips_timing_read(float* ms_host /*[TRIPS_NUM_STAGES]*/,
                                int32_t* launches_host /*[TRIPS_NUM_STAGES]*/);

@@ -313,7 +313,7 @@ class Renderer:
         return out
 
 
-NUM_STAGES = 13
+NUM_STAGES = 12
 
 
 def timing_enable(on=True):

@@ -520,28 +520,56 @@ __global__ __launch_bounds__(1024) void k_chunkscan(const uint32_t* __restrict__
   }
 }
 
-// binscan: per chunk (one wavefront), the tiles' starts and list entries.
+// binscan: per chunk (one wavefront), the tiles' starts, list entries and work items.  The
+// work table is in processing order, largest items first (size classes of item_e / NBUCKET
+// entries; the order within a class is whatever the atomics give, which changes no result:
+// every item writes its own outputs).  A slot describes item it as
+// {tile, first entry, end entry, it | (tile has several items) << 31}; slots are reserved per
+// chunk and class, with LDS counters and then one global atomic per class.
 __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot,
                                                 const uint32_t* __restrict__ coff,
                                                 uint32_t* __restrict__ bin_start,
                                                 uint32_t* __restrict__ item_start,
                                                 uint32_t* __restrict__ multi_bins,
                                                 uint4* __restrict__ fine_work,
-                                                uint32_t* __restrict__ coarse_bins, uint32_t NB,
-                                                uint32_t item_e) {
-  const uint32_t b = blockIdx.x * CHUNK + threadIdx.x;
+                                                uint32_t* __restrict__ coarse_bins,
+                                                uint32_t* __restrict__ info, uint4* __restrict__ work,
+                                                uint32_t NB, uint32_t item_e) {
+  __shared__ uint32_t s_cnt[NBUCKET], s_base[NBUCKET];
+  const int t = threadIdx.x;
+  if (t < NBUCKET) s_cnt[t] = 0;
+  const uint32_t b = blockIdx.x * CHUNK + t;
   const TileCount c = tile_count(tot, b, NB, item_e);
   const uint32_t* co = coff + size_t(blockIdx.x) * 4;
   const uint32_t oe = co[0] + wave_incl_scan(c.e) - c.e;
   const uint32_t oi = co[1] + wave_incl_scan(c.it) - c.it;
   const uint32_t om = co[2] + wave_incl_scan(c.multi) - c.multi;
   const uint32_t of = co[3] + wave_incl_scan(c.fine) - c.fine;
-  if (b >= NB) return;
-  bin_start[b] = oe;
-  item_start[b] = oi;
-  if (c.multi) multi_bins[om] = b;
-  if (c.fine) fine_work[of] = make_uint4(b, oe, oe + c.e, 0u);
-  else coarse_bins[b - of] = b;  // tiles before b that are not fine
+  if (b < NB) {
+    bin_start[b] = oe;
+    item_start[b] = oi;
+    if (c.multi) multi_bins[om] = b;
+    if (c.fine) fine_work[of] = make_uint4(b, oe, oe + c.e, 0u);
+    else coarse_bins[b - of] = b;  // tiles before b that are not fine
+  }
+  // work items: all but the last hold item_e entries (class 0)
+  const uint32_t nfull = c.it ? c.it - 1 : 0u;
+  const uint32_t elast = oe + nfull * item_e;
+  const uint32_t q = size_class(oe + c.e - elast, item_e);
+  __syncthreads();
+  const uint32_t rf = nfull ? atomicAdd(&s_cnt[0], nfull) : 0u;
+  const uint32_t rl = c.it ? atomicAdd(&s_cnt[q], 1u) : 0u;
+  __syncthreads();
+  if (t < NBUCKET && s_cnt[t])
+    s_base[t] = info[INFO_BUCKET + t] + atomicAdd(&info[INFO_BUCKET + NBUCKET + t], s_cnt[t]);
+  __syncthreads();
+  if (!c.it) return;
+  const uint32_t multi = c.it > 1 ? 0x80000000u : 0u;
+  for (uint32_t k = 0; k < nfull; ++k) {
+    const uint32_t e0 = oe + k * item_e;
+    work[s_base[0] + rf + k] = make_uint4(b, e0, e0 + item_e, (oi + k) | multi);
+  }
+  work[s_base[q] + rl] = make_uint4(b, elast, oe + c.e, (oi + c.it - 1) | multi);
 }
 
 // scatter: the count pass again, with LDS ranks; entry -> bin_start + H (column prefix) + rank.
@@ -763,45 +791,6 @@ __device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
 #pragma unroll
     for (int i = 0; i < KEEP; ++i)
       if ((i & w) == 0) cswap(k[i], g[i], k[i + w], g[i + w]);
-}
-
-// item_bins: the work table in processing order, largest items first (size classes of
-// item_e / NBUCKET entries; the order within a class is whatever the atomics give, which
-// changes no result: every item writes its own outputs).  A slot describes item it as
-// {bin, first entry, end entry, it | (bin has several items) << 31}.  Slots are reserved per
-// workgroup and class: LDS counters, then one global atomic per class.
-__global__ __launch_bounds__(256) void k_item_bins(const uint32_t* __restrict__ item_start,
-                                                   const uint32_t* __restrict__ bin_start,
-                                                   uint32_t* __restrict__ info,
-                                                   uint4* __restrict__ work, uint32_t NB,
-                                                   uint32_t item_e) {
-  __shared__ uint32_t s_cnt[NBUCKET], s_base[NBUCKET];
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (threadIdx.x < NBUCKET) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
-  uint32_t i0 = 0, i1 = 0, e_beg = 0, e_end = 0;
-  if (b < NB) {
-    i0 = item_start[b]; i1 = item_start[b + 1];
-    e_beg = bin_start[b]; e_end = bin_start[b + 1];
-  }
-  // all items but the last hold item_e entries (class 0)
-  const uint32_t nfull = i1 > i0 ? i1 - i0 - 1 : 0u;
-  const uint32_t elast = e_beg + nfull * item_e;
-  const uint32_t q = size_class(e_end - elast, item_e);
-  const uint32_t rf = nfull ? atomicAdd(&s_cnt[0], nfull) : 0u;
-  const uint32_t rl = i1 > i0 ? atomicAdd(&s_cnt[q], 1u) : 0u;
-  __syncthreads();
-  if (threadIdx.x < NBUCKET && s_cnt[threadIdx.x])
-    s_base[threadIdx.x] = info[INFO_BUCKET + threadIdx.x] +
-                          atomicAdd(&info[INFO_BUCKET + NBUCKET + threadIdx.x], s_cnt[threadIdx.x]);
-  __syncthreads();
-  if (i1 == i0) return;
-  const uint32_t multi = (i1 - i0 > 1) ? 0x80000000u : 0u;
-  for (uint32_t k = 0; k < nfull; ++k) {
-    const uint32_t e0 = e_beg + k * item_e;
-    work[s_base[0] + rf + k] = make_uint4(b, e0, e0 + item_e, (i0 + k) | multi);
-  }
-  work[s_base[q] + rl] = make_uint4(b, elast, e_end, (i1 - 1) | multi);
 }
 
 // fwd_items: one workgroup per work item (coarse layers first).  Each LDS round expands
@@ -1662,11 +1651,11 @@ thread_local int32_t g_last_hip = 0;
 
 // Optional per-kernel timing (reports only): a start and an end event around every kernel
 // launch, on the launch stream; read back and summed per stage by trips_timing_read.
-enum Stage { ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_ITEM_BINS, ST_SCATTER, ST_FWD_ITEMS,
+enum Stage { ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_SCATTER, ST_FWD_ITEMS,
              ST_FWD_FINE, ST_FWD_MERGE, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_FINE, ST_BWD_POINTS,
              ST_EXPORT, NUM_STAGES };
 const char* const kStageNames[NUM_STAGES] = {
-    "count", "colscan", "binscan", "item_bins", "scatter", "fwd_items", "fwd_fine", "fwd_merge",
+    "count", "colscan", "binscan", "scatter", "fwd_items", "fwd_fine", "fwd_merge",
     "bwd_pixels", "bwd_items", "bwd_fine", "bwd_points", "export"};
 static_assert(NUM_STAGES == TRIPS_NUM_STAGES, "stage table");
 
@@ -1911,13 +1900,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, st, csum, coff, bin_start, item_start,
                        info, P.NB, nch);
     hipLaunchKernelGGL(k_binscan, dim3(nch), dim3(CHUNK), 0, st, tot, coff, bin_start, item_start,
-                       multi_bins, fine_work, coarse_bins, P.NB, P.item_e);
-  }
-  TRIPS_HIP(hipGetLastError());
-  {
-    StageTimer tm(ST_ITEM_BINS, st);
-    hipLaunchKernelGGL(k_item_bins, dim3((P.NB + 255) / 256), dim3(256), 0, st, item_start,
-                       bin_start, info, work, P.NB, P.item_e);
+                       multi_bins, fine_work, coarse_bins, info, work, P.NB, P.item_e);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.nblk > 0) {
