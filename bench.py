@@ -39,9 +39,10 @@ def kernel_bytes(stage, w):
     """Algorithmic bytes one launch of `stage` must move (reads + writes), for the report.
 
     w: workload counts.  N points, D channels, E tile entries (E_f of them in fine tiles,
-    the tiles of at most 256 entries), K kept fragments (K_f in fine tiles), NB tiles (NB_f
-    fine), I_c work items of the other tiles, P texels inside the layers, Ppad = 256 NB,
-    nblk point blocks.  Texels of a set of tiles inside the layers are counted pro rata."""
+    the tiles of at most 256 entries, which are rendered and differentiated whole with one
+    descriptor read per entry), K kept fragments (K_f in fine tiles), NB tiles (NB_f fine),
+    I_c work items of the other tiles, P texels inside the layers, Ppad = 256 NB, nblk point
+    blocks.  Texels of a set of tiles inside the layers are counted pro rata."""
     N, D, E, Ef, K, Kf = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"]
     NB, NBf, Ic, P, nblk = w["NB"], w["NB_f"], w["I_c"], w["P"], w["nblk"]
     Ppad = 256 * NB
@@ -53,10 +54,10 @@ def kernel_bytes(stage, w):
         "colscan": 8 * nblk * NB + 4 * NB,
         "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 24 * E,
         "fwd_items": 24 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
-        "fwd_fine": 28 * Ef + (4 * D + 12) * Kf + 4 * 256 * NBf + 4 * D * Pf,
-        "bwd_pixels": 4 * Ppad + (12 + 4 * D + 8) * K + 4 * D * P,
+        "fwd_fine": (28 + 4 * D) * Ef + 12 * Kf + 4 * 256 * NBf + 4 * D * Pf,
+        "bwd_pixels": 4 * 256 * NBc + (12 + 4 * D + 8) * Kc + 4 * D * Pc,
         "bwd_items": (24 + row) * Ec + 16 * Kc + Ic * 256 * (4 + 4 * D),
-        "bwd_fine": (24 + row) * Ef + 8 * Kf + 4 * D * Pf,
+        "bwd_fine": (24 + 4 * D + row) * Ef + 4 * 256 * NBf + 4 * D * Pf,
         "bwd_points": 20 * N + row * E + 4 * (5 + D) * N,
     }
     return table.get(stage)
