@@ -584,6 +584,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
                                                          const uint32_t* __restrict__ H,
                                                          const uint32_t* __restrict__ bin_start,
                                                          Entry* __restrict__ ent,
+                                                         uint32_t* __restrict__ epos,
                                                          uint32_t* __restrict__ info) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t s_vis;
@@ -635,7 +636,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
                      e.v = ft.v;
                      e.ia = g.io[sel] * alpha;
                      e.slot = slot;
-                     ent[(STAGED ? base[lb] : bs[lb] + row[lb]) + rank] = e;
+                     const uint32_t at = (STAGED ? base[lb] : bs[lb] + row[lb]) + rank;
+                     ent[at] = e;
+                     // where the backward finds this entry's row
+                     epos[(size_t(v) * NSLOT + slot) * size_t(P.n) + size_t(p)] = at;
                    });
     vis += any ? 1u : 0u;
     x = xn; y = yn; z = zn; sw = swn; al = aln;
@@ -1375,7 +1379,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
 #pragma unroll
         for (int d = 0; d < D; ++d) tau[d] += st[h][q].y * s_G[p][d];
       }
-      float* r = rows + ((size_t(bi.v) * NSLOT + (en[h].slot & 7u)) * size_t(P.n) + en[h].idx) * RW;
+      float* r = rows + size_t(e + h * TP) * RW;  // rows in entry order
       float4* r4 = reinterpret_cast<float4*>(r);
       r4[0] = make_float4(A, Bx, By, 0.0f);
 #pragma unroll
@@ -1496,7 +1500,7 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
 #pragma unroll
     for (int d = 0; d < D; ++d) tau[d] += st[q].y * s_G[p][d];
   }
-  float* r = rows + ((size_t(bi.v) * NSLOT + (en.slot & 7u)) * size_t(P.n) + en.idx) * RW;
+  float* r = rows + size_t(e0 + t) * RW;  // rows in entry order
   float4* r4 = reinterpret_cast<float4*>(r);
   r4[0] = make_float4(A, Bx, By, 0.0f);
 #pragma unroll
@@ -1522,7 +1526,7 @@ __global__ __launch_bounds__(256) void k_bwd_points(
     const float* __restrict__ Z, const float* __restrict__ SW, const float* __restrict__ A,
     const float* __restrict__ rows, float* __restrict__ gX, float* __restrict__ gY,
     float* __restrict__ gZ, float* __restrict__ gSW, float* __restrict__ gA,
-    float* __restrict__ gD, float* __restrict__ campart) {
+    float* __restrict__ gD, const uint32_t* __restrict__ epos, float* __restrict__ campart) {
   constexpr int RW = 4 + D;
   __shared__ float s_cam[CAM ? 4 : 1][16];
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1545,21 +1549,30 @@ __global__ __launch_bounds__(256) void k_bwd_points(
       float gt[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) gt[d] = 0.0f;
+      // both layer entries' footprints and entry positions first, then their rows
+      uint32_t tm[2][4], epo[2][4];
+      const uint32_t last = uint32_t(8 * P.n * P.V) - 1u;  // row capacity (guards memory only)
+#pragma unroll
+      for (int sel = 0; sel < 2; ++sel) {
+        const int L = g.L0 + sel;
+        Foot ft;
+        const bool ok = sel < g.nl && footprint(g.x, g.y, L, layer_dim(c.W, L), layer_dim(c.H, L), ft);
+        if (ok) touches(ft, P.ltw, tm[sel]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!ok) tm[sel][q] = 0;
+          epo[sel][q] = tm[sel][q] ? min(epos[(size_t(v) * NSLOT + sel * 4 + q) * size_t(P.n) + size_t(p)], last) : 0u;
+        }
+      }
 #pragma unroll
       for (int sel = 0; sel < 2; ++sel) {
         if (sel >= g.nl) break;
         const int L = g.L0 + sel;
-        const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
-        Foot ft;
-        if (!footprint(g.x, g.y, L, WL, HL, ft)) continue;
-        uint32_t tm[4];
-        touches(ft, P.ltw, tm);
         float sA = 0.f, sBx = 0.f, sBy = 0.f;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if (!tm[q]) continue;
-          const float4* r4 = reinterpret_cast<const float4*>(
-              rows + ((size_t(v) * NSLOT + sel * 4 + q) * size_t(P.n) + p) * RW);
+          if (!tm[sel][q]) continue;
+          const float4* r4 = reinterpret_cast<const float4*>(rows + size_t(epo[sel][q]) * RW);
           const float4 h = r4[0];
           sA += h.x; sBx += h.y; sBy += h.z;
 #pragma unroll
@@ -1702,7 +1715,7 @@ struct Layout {
   uint64_t npyr;      // texels of all views and layers
   // saved buffer
   size_t s_info, s_bin_start, s_item_start, s_multi, s_fine, s_coarse, s_npix, s_kkey, s_kgam,
-      s_tables_end, s_work, s_ent;
+      s_tables_end, s_work, s_ent, s_epos;
   size_t saved_bytes;
   // workspace
   size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, ws_bytes;
@@ -1800,6 +1813,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   // point-count dependent parts
   lay.s_work = take(size_t(lay.icap) * sizeof(uint4));
   lay.s_ent = take(size_t(lay.ecap) * sizeof(Entry));
+  lay.s_epos = take(size_t(views) * NSLOT * size_t(n) * 4);
   lay.saved_bytes = o;
   o = 0;
   const size_t scratch = o;
@@ -1875,6 +1889,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   uint64_t* kkey = reinterpret_cast<uint64_t*>(sv + lay.s_kkey);
   float* kgam = reinterpret_cast<float*>(sv + lay.s_kgam);
   Entry* ent = reinterpret_cast<Entry*>(sv + lay.s_ent);
+  uint32_t* epos = reinterpret_cast<uint32_t*>(sv + lay.s_epos);
 
   if (P.nblk > 0) {
     StageTimer tm(ST_COUNT, st);
@@ -1908,11 +1923,11 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     if (staged_scatter_lds(lay.nbv_max) <= kLdsLimit)
       hipLaunchKernelGGL(k_scatter<true>, dim3(P.nblk * P.V), dim3(BIN_THREADS),
                          staged_scatter_lds(lay.nbv_max), st, P, pts.x, pts.y, pts.z, pts.size_w,
-                         pts.opacity, H, bin_start, ent, info);
+                         pts.opacity, H, bin_start, ent, epos, info);
     else
       hipLaunchKernelGGL(k_scatter<false>, dim3(P.nblk * P.V), dim3(BIN_THREADS),
                          count_lds(lay.nbv_max), st, P, pts.x, pts.y, pts.z, pts.size_w,
-                         pts.opacity, H, bin_start, ent, info);
+                         pts.opacity, H, bin_start, ent, epos, info);
   }
   TRIPS_HIP(hipGetLastError());
   {  // one workgroup per work item; workgroups beyond the item count exit at once
@@ -1951,6 +1966,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   const uint64_t* kkey = reinterpret_cast<const uint64_t*>(sv + lay.s_kkey);
   const float* kgam = reinterpret_cast<const float*>(sv + lay.s_kgam);
   const Entry* ent = reinterpret_cast<const Entry*>(sv + lay.s_ent);
+  const uint32_t* epos = reinterpret_cast<const uint32_t*>(sv + lay.s_epos);
 
   {
     StageTimer tm(ST_BWD_PIXELS, st);
@@ -1976,10 +1992,12 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     float* campart = reinterpret_cast<float*>(ws + lay.w_cam);
     if (X.gcam)
       hipLaunchKernelGGL((k_bwd_points<D, true>), dim3(nblk), dim3(256), 0, st, P, pts.x, pts.y,
-                         pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, campart);
+                         pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, epos,
+                         campart);
     else
       hipLaunchKernelGGL((k_bwd_points<D, false>), dim3(nblk), dim3(256), 0, st, P, pts.x, pts.y,
-                         pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, campart);
+                         pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, epos,
+                         campart);
   }
   TRIPS_HIP(hipGetLastError());
   if (X.gcam) {
