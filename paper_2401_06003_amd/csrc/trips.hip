@@ -47,6 +47,8 @@ constexpr uint64_t KEY_NONE = ~0ull;
 // by one workgroup with one entry per thread: its lists are sorted in LDS, and the kept slot
 // of every corner is stored in the entry for the backward pass.
 constexpr uint32_t FINE_E = 256;
+// The backward needs no merge, so its workgroups take smaller parts of the work items.
+constexpr uint32_t BWD_SPLIT = 2;
 // Work items are ordered by size class, largest first: class q holds items of more than
 // (NBUCKET - 1 - q) / NBUCKET of item_e entries.  info[INFO_BUCKET + q] is the first work
 // slot of class q, info[INFO_BUCKET + NBUCKET + q] its fill counter.
@@ -1269,7 +1271,8 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
     const Entry* __restrict__ ent,
     const uint32_t* __restrict__ npix, const uint64_t* __restrict__ kkey,
-    const float2* __restrict__ bst, const float* __restrict__ gpyr, float* __restrict__ rows) {
+    const float2* __restrict__ bst, const float* __restrict__ gpyr, float* __restrict__ rows,
+    uint32_t split) {
   constexpr int RW = 4 + D;
   constexpr int EB = 2;  // entries per thread in flight
   __shared__ uint32_t s_k[TP];
@@ -1278,9 +1281,15 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   __shared__ float s_G[TP][D + 1];
   const int t = threadIdx.x;
   const uint32_t total = info[1];
-  const uint4 wk = work[blockIdx.x];
-  if (blockIdx.x >= total) return;
-  const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z;
+  // every work item is shared by `split` workgroups, each taking an equal part of its entries
+  const uint32_t wi = blockIdx.x / split, part = blockIdx.x % split;
+  const uint4 wk = work[wi];  // in bounds (grid = split x capacity); used only if valid
+  if (wi >= total) return;
+  const uint32_t b = wk.x;
+  const uint32_t chunk = (wk.z - wk.y + split - 1) / split;
+  const uint32_t e0 = wk.y + min(wk.z - wk.y, part * chunk);
+  const uint32_t e1 = wk.y + min(wk.z - wk.y, (part + 1) * chunk);
+  if (e0 == e1) return;
   // the first entries of this thread, loaded while the tile is staged
   Entry nx[EB];
 #pragma unroll
@@ -1795,7 +1804,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.ecap = 8ull * uint64_t(n) * uint64_t(views);  // <= 2 layers x 4 tiles per point and view
   if (lay.ecap >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
   lay.icap = bins + (lay.ecap + item_e - 1) / item_e;
-  if (lay.icap >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
+  if (lay.icap * BWD_SPLIT >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
   const size_t NB = bins;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -1976,8 +1985,8 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BWD_ITEMS, st);
-    hipLaunchKernelGGL(k_bwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info, work,
-                       ent, npix, kkey, bst, gpyr, rows);
+    hipLaunchKernelGGL(k_bwd_items<D>, dim3(uint32_t(lay.icap) * BWD_SPLIT), dim3(256), 0, st, P,
+                       info, work, ent, npix, kkey, bst, gpyr, rows, BWD_SPLIT);
   }
   TRIPS_HIP(hipGetLastError());
   {
