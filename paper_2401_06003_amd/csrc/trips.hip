@@ -799,10 +799,12 @@ __device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
       if ((i & w) == 0) cswap(k[i], g[i], k[i + w], g[i + w]);
 }
 
-// fwd_items: one workgroup per work item (coarse layers first).  Each LDS round expands
-// SUB_E entries into fragments, counting-sorts them by texel and lets the thread owning the
-// texel insert them into its register top-16.  A fragment whose key is not below the
-// texel's current 16th key is only counted, never sorted.
+// fwd_items: one workgroup per work item (largest first).  Each LDS round expands SUB_E
+// entries into fragments, counting-sorts them by texel and lets the thread owning the texel
+// insert them into its register top-16; in the first round, whose lists are all empty, the
+// fragments' depth ranks are counted in LDS instead and the first 16 ranks loaded in order.
+// A fragment whose key is not below the texel's current 16th key is only counted, never
+// sorted.
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_items(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
@@ -816,6 +818,8 @@ __global__ __launch_bounds__(256) void k_fwd_items(
   __shared__ uint32_t ws[4];
   __shared__ uint64_t skey[SUB_F];
   __shared__ float sgam[SUB_F];
+  __shared__ uint8_t stex[SUB_F];   // texel of each sorted fragment (first round)
+  __shared__ uint16_t sord[SUB_F];  // at run start + r: run position of rank r (first round)
   const int t = threadIdx.x;
   const uint32_t total = info[1];
   const uint4 wk = work[blockIdx.x];  // in bounds (grid = capacity); used only if valid
@@ -877,21 +881,51 @@ __global__ __launch_bounds__(256) void k_fwd_items(
           const uint32_t o = hist[cs[c].p] + ((rank[q][c >> 1] >> ((c & 1) * 16)) & 0xffffu);
           skey[o] = key;
           sgam[o] = (cs[c].wx * cs[c].wy) * en[q].ia;
+          stex[o] = uint8_t(cs[c].p);
         }
     }
     __syncthreads();
-    // the texel's run, read from LDS four fragments at a time
-    for (uint32_t r = 0; r < cnt; r += 4) {
-      uint64_t rk[4];
-      float rg[4];
+    if (s0 == e0) {
+      // first round: every list is empty, so a texel's list is simply the first ranks of its
+      // run.  Every fragment counts the smaller keys of its run (its depth rank; keys are
+      // distinct in a texel), then each thread loads its first 16 ranks in order.
+      for (uint32_t o = t; o < tot; o += TP) {
+        const uint32_t p = stex[o];
+        const uint32_t r0 = hist[p], r1 = p + 1 < TP ? hist[p + 1] : tot;
+        const uint64_t ko = skey[o];
+        uint32_t rk = 0;
+        for (uint32_t r = r0; r < r1; r += 4) {
+          uint64_t kq[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool v = r + q < cnt;
-        rk[q] = v ? skey[base + r + q] : KEY_NONE;
-        rg[q] = v ? sgam[base + r + q] : 0.0f;
+          for (int q = 0; q < 4; ++q) kq[q] = r + q < r1 ? skey[r + q] : KEY_NONE;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) rk += kq[q] < ko ? 1u : 0u;
+        }
+        if (rk < KEEP) sord[r0 + rk] = uint16_t(o - r0);
       }
+      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) top_insert(kk, kg, rk[q], rg[q]);
+      for (int m = 0; m < KEEP; ++m) {
+        const bool v = uint32_t(m) < cnt;
+        // (the clamp only guards LDS: ranks are a permutation of the run)
+        const uint32_t o = base + (v ? min(uint32_t(sord[base + m]), cnt - 1) : 0u);
+        kk[m] = v ? skey[o] : KEY_NONE;
+        kg[m] = v ? sgam[o] : 0.0f;
+      }
+    } else {
+      // the texel's run, read from LDS four fragments at a time
+      for (uint32_t r = 0; r < cnt; r += 4) {
+        uint64_t rk[4];
+        float rg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool v = r + q < cnt;
+          rk[q] = v ? skey[base + r + q] : KEY_NONE;
+          rg[q] = v ? sgam[base + r + q] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) top_insert(kk, kg, rk[q], rg[q]);
+      }
     }
     thr[t] = kk[KEEP - 1];
 #pragma unroll
