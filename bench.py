@@ -52,13 +52,13 @@ def kernel_bytes(stage, w):
     table = {
         "count": 16 * N + 4 * nblk * NB,
         "colscan": 8 * nblk * NB + 4 * NB,
-        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 24 * E,
+        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 28 * E,
         "fwd_items": 24 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
         "fwd_fine": (28 + 4 * D) * Ef + 12 * Kf + 4 * 256 * NBf + 4 * D * Pf,
         "bwd_pixels": 4 * 256 * NBc + (12 + 4 * D + 8) * Kc + 4 * D * Pc,
         "bwd_items": (24 + row) * Ec + 16 * Kc + Ic * 256 * (4 + 4 * D),
         "bwd_fine": (24 + 4 * D + row) * Ef + 4 * 256 * NBf + 4 * D * Pf,
-        "bwd_points": 20 * N + row * E + 4 * (5 + D) * N,
+        "bwd_points": 20 * N + (4 + row) * E + 4 * (5 + D) * N,
     }
     return table.get(stage)
 
