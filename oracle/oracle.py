@@ -83,12 +83,12 @@ def _configure(L):
                                       c_int, c_double, c_int, u8p, dp, dp, dp, dp, dp, dp, dp]
         L.oracle_backward.restype = c_int
         L.oracle_forward_ex.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int,
-                                        c_int, c_int, c_double, c_int, u8p, u8p, dp, i32p, i64p,
-                                        u8p]
+                                        c_int, c_int, c_double, c_int, c_int, u8p, u8p, dp, i32p,
+                                        i64p, u8p]
         L.oracle_forward_ex.restype = c_int
         L.oracle_backward_ex.argtypes = [i64, dp, dp, dp, dp, dp, dp, c_int, dp, c_int, c_int,
-                                         c_int, c_int, c_double, c_int, u8p, u8p, dp, u8p, dp, dp,
-                                         dp, dp, dp, dp, u8p, u8p]
+                                         c_int, c_int, c_double, c_int, c_int, u8p, u8p, dp, u8p,
+                                         dp, dp, dp, dp, dp, dp, u8p, u8p]
         L.oracle_backward_ex.restype = c_int
     return L
 
@@ -215,10 +215,12 @@ def _opt(a):
     return a, ctypes.c_void_p(a.ctypes.data)
 
 
-def forward_ex(pts, cam, nlayers, background=None, maxlist=16, eps=0.25, fp32=True, mask=None):
+def forward_ex(pts, cam, nlayers, background=None, maxlist=16, eps=0.25, fp32=True, mask=None,
+               coarser=False):
     """forward() with the optional terms: background [P, D] composited behind the kept
-    list with the transmittance it leaves.  Returns dict pyr [P, D], counts, ids and alpha
-    [P] (the coverage 1 - T_K)."""
+    list with the transmittance it leaves; coarser: every texel also blends the fragments
+    of the coarser layers' texels that cover it.  Returns dict pyr [P, D], counts (own
+    fragments), ids (the blended list) and alpha [P] (the coverage 1 - T_K)."""
     n = len(pts["x"])
     X, Y, Z, S, A = (_d(pts[k]) for k in ("x", "y", "z", "sw", "alpha"))
     desc = _d(pts["desc"]).reshape(n, -1) if n else np.zeros((0, pts["desc"].shape[-1]))
@@ -231,7 +233,8 @@ def forward_ex(pts, cam, nlayers, background=None, maxlist=16, eps=0.25, fp32=Tr
     bgk, bgp = _opt(None if background is None else np.asarray(background).reshape(P, D))
     rc = lib().oracle_forward_ex(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(S), _ptr(A), _ptr(desc), D,
                                  _ptr(cv), int(cam["W"]), int(cam["H"]), int(nlayers),
-                                 int(maxlist), float(eps), int(fp32), mp, bgp, _ptr(out["pyr"]),
+                                 int(maxlist), float(eps), int(fp32), int(bool(coarser)), mp, bgp,
+                                 _ptr(out["pyr"]),
                                  _ptr(out["counts"], ctypes.c_int32),
                                  _ptr(out["ids"], ctypes.c_int64),
                                  ctypes.c_void_p(out["alpha"].ctypes.data))
@@ -240,10 +243,11 @@ def forward_ex(pts, cam, nlayers, background=None, maxlist=16, eps=0.25, fp32=Tr
 
 
 def backward_ex(pts, cam, nlayers, G, background=None, grad_alpha=None, maxlist=16, eps=0.25,
-                fp32=True, mask=None):
+                fp32=True, mask=None, coarser=False):
     """backward() with the optional terms: the background the forward composited, the
     upstream gradient of the coverage, and the gradients of the background (gbg [P, D])
-    and of the camera (gcam [16]: dR row-major, dt, dfx, dfy, dcx, dcy)."""
+    and of the camera (gcam [16]: dR row-major, dt, dfx, dfy, dcx, dcy); coarser as in
+    forward_ex."""
     n = len(pts["x"])
     X, Y, Z, S, A = (_d(pts[k]) for k in ("x", "y", "z", "sw", "alpha"))
     desc = _d(pts["desc"]).reshape(n, -1)
@@ -261,7 +265,8 @@ def backward_ex(pts, cam, nlayers, G, background=None, grad_alpha=None, maxlist=
     gak, gap = _opt(None if grad_alpha is None else np.asarray(grad_alpha).reshape(P))
     rc = lib().oracle_backward_ex(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(S), _ptr(A), _ptr(desc), D,
                                   _ptr(cv), int(cam["W"]), int(cam["H"]), int(nlayers),
-                                  int(maxlist), float(eps), int(fp32), mp, bgp, _ptr(Gd), gap,
+                                  int(maxlist), float(eps), int(fp32), int(bool(coarser)), mp, bgp,
+                                  _ptr(Gd), gap,
                                   _ptr(out["gx"]), _ptr(out["gy"]), _ptr(out["gz"]),
                                   _ptr(out["gsw"]), _ptr(out["galpha"]), _ptr(out["gdesc"]),
                                   ctypes.c_void_p(out["gbg"].ctypes.data),

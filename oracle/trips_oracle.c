@@ -16,7 +16,9 @@
  *   3. Write a bilinear 2x2 footprint in each chosen layer with beta from Eq. 4;
  *      each fragment carries gamma = beta * iota * alpha (Eq. 3).
  *   4. Collect the fragments of every (layer, pixel), sort them by depth (ties by
- *      point index) and keep the front-most 16 (Sec. 3.2).
+ *      point index) and keep the front-most 16 (Sec. 3.2).  Optionally (coarser-layer
+ *      inclusion, Sec. 3.2) the list of a texel also holds the fragments of the texels of
+ *      all coarser layers that cover it.
  *   5. Blend front to back, C = sum_m T_m gamma_m tau_m with
  *      T_m = prod_{i<m} (1 - gamma_i) (Eq. 6-7).
  *   The backward pass is the analytic adjoint of steps 3-5 and of the projection,
@@ -55,6 +57,12 @@
  *     through the transmittance the kept fragments leave (an empty list shows it whole).
  *   - the coverage output is 1 - T_K over the kept list (the blend of a constant 1).
  *   - f in Eq. 2 is f_x; points with z <= znear or non-finite x, y, s are culled.
+ *   - coarser-layer inclusion (the paper names the usual way and no more): texel
+ *     (i, j) of layer L takes in the fragments of texel (i >> k, j >> k) of layer L + k
+ *     for every k >= 1, each with its own gamma; the union is ordered by depth, then point
+ *     index, then layer (finer first: a point written to two layers appears twice), and
+ *     clamped to 16.  The per-texel count output stays the number of the texel's own
+ *     fragments.
  *
  * Compile with -O2 -ffp-contract=off and without -ffast-math.
  */
@@ -212,13 +220,23 @@ static int64_t emit_layer(const cam_t* c, const proj_t* p, int sel, int64_t idx,
   return nout;
 }
 
+/* Blend order inside one texel's list (Sec. 3.2): depth ascending, ties by point index;
+   with coarser-layer inclusion a point can appear twice (its two layers), and then the
+   fragment of the finer layer comes first. */
+static int order_cmp(const void* a, const void* b) {
+  const frag_t* x = (const frag_t*)a;
+  const frag_t* y = (const frag_t*)b;
+  if (x->z != y->z) return x->z < y->z ? -1 : 1;
+  if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+  if (x->L != y->L) return x->L < y->L ? -1 : 1;
+  return 0;
+}
+
 static int frag_cmp(const void* a, const void* b) {
   const frag_t* x = (const frag_t*)a;
   const frag_t* y = (const frag_t*)b;
   if (x->pix != y->pix) return x->pix < y->pix ? -1 : 1;
-  if (x->z != y->z) return x->z < y->z ? -1 : 1;
-  if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
-  return 0;
+  return order_cmp(a, b);
 }
 
 static void layer_bases(int W, int H, int nlayers, int64_t* base) {
@@ -255,6 +273,58 @@ static int check_args(int64_t n, int D, int W, int H, int nlayers, int maxlist) 
   if (D > 64) return 0;
   if (n < 0 || D < 1 || W < 1 || H < 1 || nlayers < 1 || nlayers > 30 || maxlist < 1) return 0;
   return 1;
+}
+
+/* Start of every texel's run in the (pixel, depth, index)-sorted fragments: run[pix] ..
+   run[pix + 1]. */
+static int64_t* texel_runs(const frag_t* fr, int64_t nf, int64_t P) {
+  int64_t* run = (int64_t*)calloc((size_t)P + 1, sizeof(int64_t));
+  if (!run) return NULL;
+  for (int64_t k = 0; k < nf; ++k) run[fr[k].pix + 1]++;
+  for (int64_t pix = 0; pix < P; ++pix) run[pix + 1] += run[pix];
+  return run;
+}
+
+/* Coarser-layer inclusion (Sec. 3.2, last paragraph): texel (i, j) of layer L also blends
+   the fragments of the texel (i >> k, j >> k) of every coarser layer L + k, the texel of
+   that layer that covers it.  Returns the list of texel pix in blend order (own fragments
+   alone without inclusion); buf has room for every fragment. */
+static const frag_t* texel_list(const frag_t* fr, const int64_t* run, const int64_t* base,
+                                int W, int nlayers, int64_t pix, int coarser, frag_t* buf,
+                                int64_t* len) {
+  if (!coarser) {
+    *len = run[pix + 1] - run[pix];
+    return fr + run[pix];
+  }
+  int L = 0;
+  while (pix >= base[L + 1]) ++L;
+  int64_t local = pix - base[L];
+  int64_t WL = layer_w(W, L);
+  int64_t i = local % WL, j = local / WL;
+  int64_t m = 0;
+  for (int k = 0; L + k < nlayers; ++k) {
+    int64_t q = base[L + k] + (j >> k) * layer_w(W, L + k) + (i >> k);
+    for (int64_t a = run[q]; a < run[q + 1]; ++a) buf[m++] = fr[a];
+  }
+  qsort(buf, (size_t)m, sizeof(frag_t), order_cmp);
+  *len = m;
+  return buf;
+}
+
+/* With inclusion, the fragments a masked texel needs lie in it and in its ancestors. */
+static uint8_t* ancestor_mask(const uint8_t* mask, int W, int H, int nlayers) {
+  int64_t base[33];
+  layer_bases(W, H, nlayers, base);
+  uint8_t* m = (uint8_t*)malloc((size_t)base[nlayers]);
+  if (!m) return NULL;
+  memcpy(m, mask, (size_t)base[nlayers]);
+  for (int L = 0; L + 1 < nlayers; ++L) {
+    int64_t WL = layer_w(W, L), HL = layer_w(H, L), WP = layer_w(W, L + 1);
+    for (int64_t j = 0; j < HL; ++j)
+      for (int64_t i = 0; i < WL; ++i)
+        if (m[base[L] + j * WL + i]) m[base[L + 1] + (j >> 1) * WP + (i >> 1)] = 1;
+  }
+  return m;
 }
 
 /* Number of texels of all layers of a W x H view. */
@@ -311,45 +381,47 @@ int64_t oracle_fragments(int64_t n, const double* X, const double* Y, const doub
 }
 
 /* Forward, one view.  pyr: [sum_L H_L W_L][D] (layers concatenated, each row-major);
-   counts: untruncated list length per texel; ids: [P][maxlist] kept point indices in
-   blend order, -1 padded.  mask (optional, [P] bytes): only texels with a non-zero
-   mask byte are evaluated; the others are left at 0 / -1.  bg (optional, [P][D]):
-   background composited behind the kept list; alpha (optional, [P]): coverage
-   1 - T_K.  Texels outside the mask keep bg = 0 and alpha = 0 too. */
+   counts: untruncated number of the texel's own fragments; ids: [P][maxlist] kept point
+   indices in blend order, -1 padded.  mask (optional, [P] bytes): only texels with a
+   non-zero mask byte are evaluated; the others are left at 0 / -1.  bg (optional, [P][D]):
+   background composited behind the kept list; alpha (optional, [P]): coverage 1 - T_K.
+   Texels outside the mask keep bg = 0 and alpha = 0 too.  coarser: blend each texel's
+   fragments together with those of the texels of coarser layers that cover it. */
 int oracle_forward_ex(int64_t n, const double* X, const double* Y, const double* Z,
                       const double* SW, const double* A, const double* DESC, int D,
                       const double* cam, int W, int H, int nlayers, int maxlist, double eps,
-                      int fp32, const uint8_t* mask, const double* bg, double* pyr,
+                      int fp32, int coarser, const uint8_t* mask, const double* bg, double* pyr,
                       int32_t* counts, int64_t* ids, double* alpha) {
   if (!check_args(n, D, W, H, nlayers, maxlist)) return OR_ERR_ARG;
   cam_t c;
   unpack_cam(cam, W, H, &c);
   int64_t P = oracle_num_pixels(W, H, nlayers);
+  int64_t base[33];
+  layer_bases(W, H, nlayers, base);
   memset(pyr, 0, (size_t)P * D * sizeof(double));
   memset(counts, 0, (size_t)P * sizeof(int32_t));
   if (alpha) memset(alpha, 0, (size_t)P * sizeof(double));
   for (int64_t k = 0; k < P * maxlist; ++k) ids[k] = -1;
-  /* an empty list shows the whole background */
-  if (bg)
-    for (int64_t pix = 0; pix < P; ++pix)
-      if (!mask || mask[pix])
-        for (int d = 0; d < D; ++d) pyr[pix * D + d] = bg[pix * D + d];
+  uint8_t* cmask = (coarser && mask) ? ancestor_mask(mask, W, H, nlayers) : NULL;
+  if (coarser && mask && !cmask) return OR_ERR_MEM;
   int64_t nf = 0;
-  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, mask, &nf, NULL);
+  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, cmask ? cmask : mask, &nf, NULL);
+  free(cmask);
   if (!fr) return OR_ERR_MEM;
-  int64_t a = 0;
-  while (a < nf) {
-    int64_t b = a;
-    while (b < nf && fr[b].pix == fr[a].pix) ++b;
-    int64_t pix = fr[a].pix;
-    int64_t len = b - a;
-    counts[pix] = (int32_t)len;
+  int64_t* run = texel_runs(fr, nf, P);
+  frag_t* buf = (frag_t*)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(frag_t));
+  if (!run || !buf) { free(fr); free(run); free(buf); return OR_ERR_MEM; }
+  for (int64_t pix = 0; pix < P; ++pix) {
+    if (mask && !mask[pix]) continue;
+    int64_t len = 0;
+    const frag_t* list = texel_list(fr, run, base, W, nlayers, pix, coarser, buf, &len);
+    counts[pix] = (int32_t)(run[pix + 1] - run[pix]);
     int64_t keep = len < maxlist ? len : maxlist;
     double T = 1.0;
     double col[64];
     for (int d = 0; d < D; ++d) col[d] = 0.0;
     for (int64_t m = 0; m < keep; ++m) {
-      const frag_t* f = &fr[a + m];
+      const frag_t* f = &list[m];
       ids[pix * maxlist + m] = f->idx;
       double w = T * f->gamma;
       for (int d = 0; d < D; ++d) {
@@ -358,11 +430,11 @@ int oracle_forward_ex(int64_t n, const double* X, const double* Y, const double*
       }
       T = T * (1.0 - f->gamma);
     }
+    /* an empty list shows the whole background */
     for (int d = 0; d < D; ++d) pyr[pix * D + d] = col[d] + (bg ? T * bg[pix * D + d] : 0.0);
     if (alpha) alpha[pix] = 1.0 - T;
-    a = b;
   }
-  free(fr);
+  free(fr); free(run); free(buf);
   return OR_OK;
 }
 
@@ -371,7 +443,7 @@ int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z,
                    int nlayers, int maxlist, double eps, int fp32, const uint8_t* mask,
                    double* pyr, int32_t* counts, int64_t* ids) {
   return oracle_forward_ex(n, X, Y, Z, SW, A, DESC, D, cam, W, H, nlayers, maxlist, eps, fp32,
-                           mask, NULL, pyr, counts, ids, NULL);
+                           0, mask, NULL, pyr, counts, ids, NULL);
 }
 
 /* Backward, one view: gradients of sum(G * pyr) (+ sum(Galpha * alpha) when Galpha is
@@ -381,45 +453,51 @@ int oracle_forward(int64_t n, const double* X, const double* Y, const double* Z,
    Outputs are overwritten.  The depth order, culling and the 16-element clamp are
    piecewise constant and carry no gradient; fragments beyond the clamp get none.
    mask (optional): only texels with a non-zero mask byte contribute, so a point's
-   gradient is exact when every texel it writes is in the mask. */
+   gradient is exact when every texel it writes is in the mask (with inclusion: every
+   texel whose list can hold its fragments).  coarser: as in oracle_forward_ex; a
+   fragment included in finer texels' lists collects the adjoint of every list it is
+   kept in. */
 int oracle_backward_ex(int64_t n, const double* X, const double* Y, const double* Z,
                        const double* SW, const double* A, const double* DESC, int D,
                        const double* cam, int W, int H, int nlayers, int maxlist, double eps,
-                       int fp32, const uint8_t* mask, const double* bg, const double* G,
-                       const double* Galpha, double* gX, double* gY, double* gZ, double* gSW,
-                       double* gA, double* gDESC, double* gbg, double* gcam) {
+                       int fp32, int coarser, const uint8_t* mask, const double* bg,
+                       const double* G, const double* Galpha, double* gX, double* gY, double* gZ,
+                       double* gSW, double* gA, double* gDESC, double* gbg, double* gcam) {
   if (!check_args(n, D, W, H, nlayers, maxlist)) return OR_ERR_ARG;
   cam_t c;
   unpack_cam(cam, W, H, &c);
   int64_t P = oracle_num_pixels(W, H, nlayers);
+  int64_t base[33];
+  layer_bases(W, H, nlayers, base);
+  uint8_t* cmask = (coarser && mask) ? ancestor_mask(mask, W, H, nlayers) : NULL;
+  if (coarser && mask && !cmask) return OR_ERR_MEM;
   int64_t nf = 0;
   proj_t* pr = NULL;
-  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, mask, &nf, &pr);
+  frag_t* fr = collect(n, X, Y, Z, SW, A, &c, nlayers, eps, fp32, cmask ? cmask : mask, &nf, &pr);
+  free(cmask);
   if (!fr) return OR_ERR_MEM;
   double* gxs = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* gys = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* gss = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* Tm = (double*)malloc((size_t)maxlist * sizeof(double));
-  if (!gxs || !gys || !gss || !Tm) { free(fr); free(pr); free(gxs); free(gys); free(gss); free(Tm); return OR_ERR_MEM; }
+  int64_t* run = texel_runs(fr, nf, P);
+  frag_t* buf = (frag_t*)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(frag_t));
+  if (!gxs || !gys || !gss || !Tm || !run || !buf) {
+    free(fr); free(pr); free(gxs); free(gys); free(gss); free(Tm); free(run); free(buf);
+    return OR_ERR_MEM;
+  }
   memset(gA, 0, (size_t)n * sizeof(double));
   memset(gDESC, 0, (size_t)n * D * sizeof(double));
   if (gcam) memset(gcam, 0, 16 * sizeof(double));
-  if (gbg) {  /* an empty list shows the whole background: dL/dbg = G */
-    memset(gbg, 0, (size_t)P * D * sizeof(double));
-    for (int64_t pix = 0; pix < P; ++pix)
-      if (!mask || mask[pix])
-        for (int d = 0; d < D; ++d) gbg[pix * D + d] = G[pix * D + d];
-  }
-  int64_t a = 0;
-  while (a < nf) {
-    int64_t b = a;
-    while (b < nf && fr[b].pix == fr[a].pix) ++b;
-    int64_t pix = fr[a].pix;
-    int64_t len = b - a;
+  if (gbg) memset(gbg, 0, (size_t)P * D * sizeof(double));
+  for (int64_t pix = 0; pix < P; ++pix) {
+    if (mask && !mask[pix]) continue;
+    int64_t len = 0;
+    const frag_t* list = texel_list(fr, run, base, W, nlayers, pix, coarser, buf, &len);
     int64_t keep = len < maxlist ? len : maxlist;
     const double* g = &G[pix * D];
     double T = 1.0;
-    for (int64_t m = 0; m < keep; ++m) { Tm[m] = T; T = T * (1.0 - fr[a + m].gamma); }
+    for (int64_t m = 0; m < keep; ++m) { Tm[m] = T; T = T * (1.0 - list[m].gamma); }
     if (gbg)
       for (int d = 0; d < D; ++d) gbg[pix * D + d] = T * g[d];
     /* Reverse sweep.  With g_m = G . tau_m (+ Galpha: the coverage blends a constant 1),
@@ -432,7 +510,7 @@ int oracle_backward_ex(int64_t n, const double* X, const double* Y, const double
     if (bg)
       for (int d = 0; d < D; ++d) B += g[d] * bg[pix * D + d];
     for (int64_t m = keep - 1; m >= 0; --m) {
-      const frag_t* f = &fr[a + m];
+      const frag_t* f = &list[m];
       int64_t p = f->idx;
       double gm = 0.0;
       for (int d = 0; d < D; ++d) {
@@ -455,7 +533,6 @@ int oracle_backward_ex(int64_t n, const double* X, const double* Y, const double
       gys[p] += dgam * iota * alpha * f->wx * sy * scale;
       gss[p] += dgam * f->wx * f->wy * alpha * q->diota[f->sel];
     }
-    a = b;
   }
   for (int64_t p = 0; p < n; ++p) {
     gX[p] = gY[p] = gZ[p] = gSW[p] = 0.0;
@@ -490,7 +567,7 @@ int oracle_backward_ex(int64_t n, const double* X, const double* Y, const double
       gcam[15] += gys[p];
     }
   }
-  free(fr); free(pr); free(gxs); free(gys); free(gss); free(Tm);
+  free(fr); free(pr); free(gxs); free(gys); free(gss); free(Tm); free(run); free(buf);
   return OR_OK;
 }
 
@@ -500,5 +577,5 @@ int oracle_backward(int64_t n, const double* X, const double* Y, const double* Z
                     const double* G, double* gX, double* gY, double* gZ, double* gSW, double* gA,
                     double* gDESC) {
   return oracle_backward_ex(n, X, Y, Z, SW, A, DESC, D, cam, W, H, nlayers, maxlist, eps, fp32,
-                            mask, NULL, G, NULL, gX, gY, gZ, gSW, gA, gDESC, NULL, NULL);
+                            0, mask, NULL, G, NULL, gX, gY, gZ, gSW, gA, gDESC, NULL, NULL);
 }

@@ -27,8 +27,8 @@ MUTATIONS = [
      "if (x->z != y->z) return x->z > y->z ? -1 : 1;"),
     ("index tie order reversed", "if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;",
      "if (x->idx != y->idx) return x->idx > y->idx ? -1 : 1;"),
-    ("transmittance not updated", "      T = T * (1.0 - f->gamma);\n    }\n    for (int d = 0; d < D; ++d) pyr",
-     "    }\n    for (int d = 0; d < D; ++d) pyr"),
+    ("transmittance not updated", "      T = T * (1.0 - f->gamma);\n    }\n    /* an empty list",
+     "    }\n    /* an empty list"),
     ("weight drops beta", "f->gamma = ((wx * wy) * p->iota[sel]) * alpha;",
      "f->gamma = p->iota[sel] * alpha;"),
     ("adjoint recurrence sign", "double dgam = Tm[m] * (gm - B);", "double dgam = Tm[m] * (gm + B);"),
@@ -49,12 +49,20 @@ MUTATIONS = [
     ("rotation gradient transposed", "gcam[3 * r + k] += dX[r] * Xw[k];", "gcam[3 * k + r] += dX[r] * Xw[k];"),
     ("focal gradient drops size term", "gcam[12] += gxs[p] * q->Xc / Zc + gss[p] * sw / Zc;",
      "gcam[12] += gxs[p] * q->Xc / Zc;"),
+    ("inclusion: coarser layer first on ties", "if (x->L != y->L) return x->L < y->L ? -1 : 1;",
+     "if (x->L != y->L) return x->L > y->L ? -1 : 1;"),
+    ("inclusion: wrong covering texel", "int64_t q = base[L + k] + (j >> k) * layer_w(W, L + k) + (i >> k);",
+     "int64_t q = base[L + k] + (j >> k) * layer_w(W, L + k) + ((i + 1) >> k);"),
+    ("inclusion: parent layer only", "for (int k = 0; L + k < nlayers; ++k) {",
+     "for (int k = 0; L + k < nlayers && k < 2; ++k) {"),
+    ("inclusion: mask misses ancestors", "if (m[base[L] + j * WL + i]) m[base[L + 1] + (j >> 1) * WP + (i >> 1)] = 1;",
+     "if (m[base[L] + j * WL + i]) m[base[L + 1] + (j >> 1) * WP + (i >> 1)] = 0;"),
     ("principal point gradient swapped", "gcam[14] += gxs[p];\n      gcam[15] += gys[p];",
      "gcam[14] += gys[p];\n      gcam[15] += gxs[p];"),
 ]
 
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_backward.py",
-             "tests/test_oracle_extras.py"]
+             "tests/test_oracle_extras.py", "tests/test_oracle_coarser.py"]
 
 
 def _run_pins_with(lib_path):
