@@ -58,12 +58,21 @@ typedef struct {
   float znear;
 } trips_camera;
 
-/* Renderer hyper-parameters (Sec. 3.1-3.2). */
+/* Renderer hyper-parameters (Sec. 3.1-3.2).
+   include_coarser (0 or 1; zero-initialised configs leave it off): coarser-layer inclusion
+   of Sec. 3.2.  The list blended at texel (i, j) of layer L then holds, besides the
+   texel's own fragments, the fragments of texel (i >> k, j >> k) of every coarser layer
+   L + k, each with its own gamma; the union is ordered by depth, point index, then layer
+   (finer first; a point written to two layers can appear twice) and clamped to
+   TRIPS_KEEP.  Gradients flow to every fragment through every list that keeps it.  It
+   adds 196 B per texel of every tile to `saved` and two tables of 16 (1 + D) floats per
+   texel of every tile to the backward part of `workspace`. */
 typedef struct {
   int32_t num_layers; /* pyramid layers n, 1..TRIPS_MAX_LAYERS; texel size of layer L is 2^L */
   int32_t max_list;   /* must be TRIPS_KEEP (16) */
   float eps;          /* minimum layer weight for points smaller than a pixel (0.25) */
   int32_t desc_dim;   /* descriptor channels D: 4 or 8 */
+  int32_t include_coarser;
 } trips_config;
 
 /* Point cloud, structure of arrays, all float32 device arrays of length n; desc is
@@ -150,9 +159,10 @@ trips_status trips_backward(const trips_config* cfg_host, const trips_points* pt
                             const trips_extras* extras_host, hipStream_t stream);
 
 /* Parity export of the fragment lists of the forward call that filled `saved`.
-   counts: int32 [P] untruncated list length per texel; ids: int32 [P][16] kept point
-   indices front to back (depth ascending, ties by index), -1 padded.  P = texels of all
-   views and layers in pyramid order. */
+   counts: int32 [P] untruncated number of each texel's own fragments; ids: int32 [P][16]
+   the point indices of the blended list front to back (depth ascending, ties by index;
+   with include_coarser, the list with the coarser layers' fragments), -1 padded.  P =
+   texels of all views and layers in pyramid order. */
 trips_status trips_export_fragments(const trips_config* cfg_host, const trips_camera* cams_host,
                                     int32_t views, const trips_tuning* tuning_host,
                                     const void* saved, size_t saved_bytes, int32_t* counts,
@@ -186,7 +196,7 @@ int32_t trips_last_hip_error(void);
    milliseconds and the number of launches since the last read (or enable), then resets.
    Stage k is named by trips_stage_name(k), k < TRIPS_NUM_STAGES.  The events are host
    objects owned by the library; no device memory is allocated. */
-#define TRIPS_NUM_STAGES 12
+#define TRIPS_NUM_STAGES 14
 trips_status trips_timing_enable(int32_t enable);
 trips_status trips_timing_read(float* ms_host /*[TRIPS_NUM_STAGES]*/,
                                int32_t* launches_host /*[TRIPS_NUM_STAGES]*/);

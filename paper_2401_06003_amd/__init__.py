@@ -26,7 +26,7 @@ class Camera(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("num_layers", c_int32), ("max_list", c_int32), ("eps", c_float),
-                ("desc_dim", c_int32)]
+                ("desc_dim", c_int32), ("include_coarser", c_int32)]
 
 
 class Points(ctypes.Structure):
@@ -126,8 +126,9 @@ def make_camera(cam):
     return c
 
 
-def make_config(num_layers, desc_dim, eps=0.25, max_list=KEEP):
-    return Config(int(num_layers), int(max_list), float(eps), int(desc_dim))
+def make_config(num_layers, desc_dim, eps=0.25, max_list=KEEP, include_coarser=False):
+    return Config(int(num_layers), int(max_list), float(eps), int(desc_dim),
+                  int(bool(include_coarser)))
 
 
 def make_tuning(tile_w=0, points_per_block=0, item_entries=0):
@@ -175,10 +176,12 @@ def _aligned_bytes(nbytes, device):
 class Renderer:
     """Renders one or more views (different resolutions allowed) of a point cloud.
 
-    Owns the `saved` and `workspace` device buffers (torch tensors) sized by the library."""
+    Owns the `saved` and `workspace` device buffers (torch tensors) sized by the library.
+    include_coarser: coarser-layer inclusion (Sec. 3.2): every texel also blends the
+    fragments of the coarser layers' texels that cover it."""
 
     def __init__(self, cams, num_layers, desc_dim, n_points, eps=0.25, tuning=None,
-                 device="cuda", share_buffers_with=None):
+                 device="cuda", share_buffers_with=None, include_coarser=False):
         if isinstance(cams, dict):
             cams = [cams]
         if not 1 <= len(cams) <= MAX_VIEWS:
@@ -186,7 +189,7 @@ class Renderer:
         self.cams_py = cams
         self.V = len(cams)
         self.cams = (Camera * self.V)(*[make_camera(c) for c in cams])
-        self.cfg = make_config(num_layers, desc_dim, eps)
+        self.cfg = make_config(num_layers, desc_dim, eps, include_coarser=include_coarser)
         self.tune = tuning if tuning is not None else make_tuning()
         self.n = int(n_points)
         self.D = int(desc_dim)
@@ -313,7 +316,7 @@ class Renderer:
         return out
 
 
-NUM_STAGES = 12
+NUM_STAGES = 14
 
 
 def timing_enable(on=True):

@@ -45,7 +45,9 @@ constexpr int MAXL = TRIPS_MAX_LAYERS;
 constexpr uint64_t KEY_NONE = ~0ull;
 // A tile with at most FINE_E entries ("fine" tile, typical of the finest layers) is rendered
 // by one workgroup with one entry per thread: its lists are sorted in LDS, and the kept slot
-// of every corner is stored in the entry for the backward pass.
+// of every corner is stored in the entry for the backward pass.  With coarser-layer
+// inclusion only empty tiles take that path (the backward of every other tile then reads
+// per-slot adjoints that the inclusion pass accumulates).
 constexpr uint32_t FINE_E = 256;
 // The backward needs no merge, so its workgroups take smaller parts of the work items.
 constexpr uint32_t BWD_SPLIT = 2;
@@ -72,6 +74,8 @@ struct Params {
   int32_t V, nl, D, ltw;  // ltw = log2(tile width); tile height = 256 >> ltw
   float eps;
   uint32_t pb, nblk, NB, item_e;
+  int32_t coarser;        // coarser-layer inclusion on
+  uint32_t fine_e;        // tiles with at most fine_e entries take the fine path
   int64_t n;
   ViewP view[MAXV];
 };
@@ -428,11 +432,11 @@ __device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) {
 
 struct TileCount { uint32_t e, it, multi, fine; };
 __device__ __forceinline__ TileCount tile_count(const uint32_t* __restrict__ tot, uint32_t b,
-                                                uint32_t NB, uint32_t item_e) {
+                                                uint32_t NB, uint32_t item_e, uint32_t fine_e) {
   TileCount r{0u, 0u, 0u, 0u};
   if (b < NB) {
     r.e = tot[b];
-    r.fine = r.e <= FINE_E ? 1u : 0u;
+    r.fine = r.e <= fine_e ? 1u : 0u;
     r.it = r.fine ? 0u : ceil_div(r.e, item_e);
     r.multi = r.it > 1 ? 1u : 0u;
   }
@@ -448,9 +452,9 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // chunksum: per chunk, the four sums and the items per size class.
 __global__ __launch_bounds__(64) void k_chunksum(const uint32_t* __restrict__ tot,
                                                  uint32_t* __restrict__ csum, uint32_t NB,
-                                                 uint32_t item_e) {
+                                                 uint32_t item_e, uint32_t fine_e) {
   const uint32_t b = blockIdx.x * CHUNK + threadIdx.x;
-  const TileCount c = tile_count(tot, b, NB, item_e);
+  const TileCount c = tile_count(tot, b, NB, item_e, fine_e);
   // it - 1 items of item_e entries (class 0) and a last one of the rest
   const uint32_t cls = c.it ? size_class(c.e - (c.it - 1) * item_e, item_e) : 0u;
   uint32_t v[CSUM];
@@ -536,12 +540,12 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
                                                 uint4* __restrict__ fine_work,
                                                 uint32_t* __restrict__ coarse_bins,
                                                 uint32_t* __restrict__ info, uint4* __restrict__ work,
-                                                uint32_t NB, uint32_t item_e) {
+                                                uint32_t NB, uint32_t item_e, uint32_t fine_e) {
   __shared__ uint32_t s_cnt[NBUCKET], s_base[NBUCKET];
   const int t = threadIdx.x;
   if (t < NBUCKET) s_cnt[t] = 0;
   const uint32_t b = blockIdx.x * CHUNK + t;
-  const TileCount c = tile_count(tot, b, NB, item_e);
+  const TileCount c = tile_count(tot, b, NB, item_e, fine_e);
   const uint32_t* co = coff + size_t(blockIdx.x) * 4;
   const uint32_t oe = co[0] + wave_incl_scan(c.e) - c.e;
   const uint32_t oi = co[1] + wave_incl_scan(c.it) - c.it;
@@ -1170,9 +1174,12 @@ __global__ __launch_bounds__(256) void k_fwd_merge(
   }
 }
 
-// export: counts and kept ids in pyramid texel order.
+// export: counts and blended ids in pyramid texel order (with coarser-layer inclusion the
+// blended list is fkey, its length in fcnt).
 __global__ __launch_bounds__(256) void k_export(const Params P, const uint32_t* __restrict__ npix,
                                                 const uint64_t* __restrict__ kkey,
+                                                const uint64_t* __restrict__ fkey,
+                                                const uint32_t* __restrict__ fcnt,
                                                 int32_t* __restrict__ counts,
                                                 int32_t* __restrict__ ids) {
   const uint32_t b = blockIdx.x;
@@ -1185,8 +1192,11 @@ __global__ __launch_bounds__(256) void k_export(const Params P, const uint32_t* 
   const size_t o = size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i;
   const uint32_t n = npix[size_t(b) * TP + t];
   counts[o] = int32_t(n);
+  const uint32_t fc = P.coarser ? fcnt[size_t(b) * TP + t] : 0u;
+  const uint32_t k = P.coarser ? (fc & 31u) + ((fc >> 5) & 31u) : n;
+  const uint64_t* key = P.coarser ? fkey : kkey;
   for (int m = 0; m < KEEP; ++m)
-    ids[o * KEEP + m] = uint32_t(m) < n ? int32_t(uint32_t(kkey[(size_t(b) * KEEP + m) * TP + t])) : -1;
+    ids[o * KEEP + m] = uint32_t(m) < k ? int32_t(uint32_t(key[(size_t(b) * KEEP + m) * TP + t])) : -1;
 }
 
 // g_m = G . tau_m, summed in one fixed order.
@@ -1299,15 +1309,19 @@ __global__ __launch_bounds__(256) void k_bwd_pixels(const Params P, const uint32
 // its partial-gradient row: (A, Bx, By, 0, tau[D]) with A = sum dgamma wx wy,
 // Bx = sum dgamma sx wy, By = sum dgamma wx sy, tau = sum T_m gamma_m G over its corners.
 // A corner is kept iff its key is not above the texel's last kept key (the kept set is the
-// 16 smallest keys); its position among the kept is found by point index.
-template <int D>
+// 16 smallest keys); its position among the kept is found by point index.  With
+// coarser-layer inclusion (INC) the kept own fragments are those the blended list took
+// (a prefix of the own list), and each one's totals (dL/dgamma, tau part) are read from
+// itot instead of being formed from the blend adjoint and G.
+template <int D, bool INC>
 __global__ __launch_bounds__(256) void k_bwd_items(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
     const Entry* __restrict__ ent,
     const uint32_t* __restrict__ npix, const uint64_t* __restrict__ kkey,
     const float2* __restrict__ bst, const float* __restrict__ gpyr, float* __restrict__ rows,
-    uint32_t split) {
+    uint32_t split, const uint32_t* __restrict__ fcnt, const float* __restrict__ itot) {
   constexpr int RW = 4 + D;
+  constexpr int S = D + 1;
   constexpr int EB = 2;  // entries per thread in flight
   __shared__ uint32_t s_k[TP];
   __shared__ uint64_t s_last[TP];
@@ -1332,8 +1346,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   const BinInfo bi = decode_bin(P, b);
   const int lth = 8 - P.ltw;
   {  // stage the tile's kept point ids, last kept keys and upstream gradient
-    const uint32_t n = npix[size_t(b) * TP + t];
-    const uint32_t k = min(n, uint32_t(KEEP));
+    const uint32_t k = INC ? (fcnt[size_t(b) * TP + t] & 31u) : min(npix[size_t(b) * TP + t], uint32_t(KEEP));
     s_k[t] = k;
     uint64_t last = 0;
     uint32_t ids[KEEP];
@@ -1353,7 +1366,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     s_last[t] = last;
     const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
     const int j = (bi.ty << lth) + (t >> P.ltw);
-    if (k > 0) {  // texels with fragments lie inside the layer
+    if (!INC && k > 0) {  // texels with fragments lie inside the layer
       const size_t o = (size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i) * D;
 #pragma unroll
       for (int d = 0; d < D; ++d) s_G[t][d] = gpyr[o + d];
@@ -1395,15 +1408,26 @@ __global__ __launch_bounds__(256) void k_bwd_items(
           }
         }
         if (m == kp) cm[h] &= ~(1u << q);
-        else pos[h][q] = (size_t(b) * KEEP + m) * TP + uint32_t(p);
+        else pos[h][q] = INC ? (size_t(b) * KEEP + m) * S * TP + uint32_t(p)
+                             : (size_t(b) * KEEP + m) * TP + uint32_t(p);
       }
     }
     float2 st[EB][4];
+    float itau[INC ? EB : 1][4][INC ? D : 1];
 #pragma unroll
     for (int h = 0; h < EB; ++h)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        st[h][q] = ((cm[h] >> q) & 1u) ? bst[pos[h][q]] : make_float2(0.f, 0.f);
+      for (int q = 0; q < 4; ++q) {
+        const bool on = (cm[h] >> q) & 1u;
+        if (INC) {
+          st[h][q] = make_float2(on ? itot[pos[h][q]] : 0.0f, 0.0f);
+#pragma unroll
+          for (int d = 0; d < D; ++d)
+            itau[INC ? h : 0][q][INC ? d : 0] = on ? itot[pos[h][q] + size_t(1 + d) * TP] : 0.0f;
+        } else {
+          st[h][q] = on ? bst[pos[h][q]] : make_float2(0.f, 0.f);
+        }
+      }
 #pragma unroll
     for (int h = 0; h < EB; ++h) {
       if (!valid[h]) continue;
@@ -1420,7 +1444,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
         Bx += dg * (cs[h][q].sx * cs[h][q].wy);
         By += dg * (cs[h][q].wx * cs[h][q].sy);
 #pragma unroll
-        for (int d = 0; d < D; ++d) tau[d] += st[h][q].y * s_G[p][d];
+        for (int d = 0; d < D; ++d) tau[d] += INC ? itau[INC ? h : 0][q][INC ? d : 0] : st[h][q].y * s_G[p][d];
       }
       float* r = rows + size_t(e + h * TP) * RW;  // rows in entry order
       float4* r4 = reinterpret_cast<float4*>(r);
@@ -1556,6 +1580,286 @@ __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
+}
+
+// ------------------------------------------------------------------------------------
+// Coarser-layer inclusion (Sec. 3.2).  The list blended at texel (i, j) of layer L is the
+// texel's own kept list merged with the blended list of the covering texel (i/2, j/2) of
+// layer L + 1, which by induction holds the fragments of every coarser layer: the 16
+// smallest of a union are the 16 smallest of the union of the parts' 16 smallest.  The
+// merge is stable and takes the own fragment first on equal keys (a point written to two
+// layers meets itself; the finer layer comes first), so the order inside the covering
+// list is kept.  Per texel the blended list is saved as fkey / fgam and
+// fcnt = own count | coarser count << 5 | (bit m: item m came from the coarser list) << 16;
+// the items taken from either side are a prefix of that side.
+
+// Tile and texel slot of texel (i, j) of layer L of view v.
+__device__ __forceinline__ void texel_bin(const Params& P, int v, int L, int i, int j,
+                                          uint32_t& b, int& t) {
+  const int lth = 8 - P.ltw;
+  const int WL = layer_dim(P.view[v].W, L);
+  const int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
+  b = P.view[v].lbin[L] + uint32_t((j >> lth) * tiles_x + (i >> P.ltw));
+  t = ((j & ((1 << lth) - 1)) << P.ltw) | (i & ((1 << P.ltw) - 1));
+}
+
+constexpr int PT = TP / 4;  // covering texels of one tile in the next coarser layer
+
+// incl_fwd: one launch per layer, coarsest first; one workgroup per tile of the layer
+// (grid.y = view).  The coarsest layer's blended list is its own (copied); every finer
+// texel merges its own list (staged in LDS) with its covering texel's blended list
+// (the tile's 64 covering texels staged in LDS), blends the result (Eq. 6-7) and rewrites
+// its outputs.
+template <int D>
+__global__ __launch_bounds__(256) void k_incl_fwd(
+    const Params P, int L, const uint32_t* __restrict__ npix, const uint64_t* __restrict__ kkey,
+    const float* __restrict__ kgam, uint64_t* __restrict__ fkey, float* __restrict__ fgam,
+    uint32_t* __restrict__ fcnt, const float* __restrict__ desc, float* __restrict__ pyr,
+    const float* __restrict__ bg, float* __restrict__ alpha) {
+  __shared__ uint64_t s_ok[KEEP][TP];
+  __shared__ float s_og[KEEP][TP];
+  __shared__ uint64_t s_pk[KEEP][PT];
+  __shared__ float s_pg[KEEP][PT];
+  __shared__ uint32_t s_pn[PT];
+  const int v = blockIdx.y;
+  const ViewP& c = P.view[v];
+  const uint32_t local = blockIdx.x;
+  if (local >= c.lbin[L + 1] - c.lbin[L]) return;  // uniform per workgroup
+  const uint32_t b = c.lbin[L] + local;
+  const int t = threadIdx.x;
+  const int lth = 8 - P.ltw;
+  const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
+  const int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
+  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  const int i = (tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int j = (ty << lth) + (t >> P.ltw);
+  const bool in = i < WL && j < HL;
+  const size_t tb = size_t(b) * KEEP;
+  const uint32_t ko = in ? min(npix[size_t(b) * TP + t], uint32_t(KEEP)) : 0u;
+  if (L == P.nl - 1) {  // uniform: the coarsest layer blends its own list (already written)
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m)
+      if (uint32_t(m) < ko) {
+        fkey[(tb + m) * TP + t] = kkey[(tb + m) * TP + t];
+        fgam[(tb + m) * TP + t] = kgam[(tb + m) * TP + t];
+      }
+    fcnt[size_t(b) * TP + t] = ko;
+    return;
+  }
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m)
+    if (uint32_t(m) < ko) {
+      s_ok[m][t] = kkey[(tb + m) * TP + t];
+      s_og[m][t] = kgam[(tb + m) * TP + t];
+    }
+  {  // the covering texels: (tw/2) x (th/2) texels of one tile of layer L + 1
+    const int hw = 1 << (P.ltw - 1);
+    const int q = t & (PT - 1), g = t >> 6;  // texel q, slots g, g+4, g+8, g+12
+    const int pi = (tx << (P.ltw - 1)) + (q & (hw - 1));
+    const int pj = (ty << (lth - 1)) + (q >> (P.ltw - 1));
+    const bool pin = pi < layer_dim(c.W, L + 1) && pj < layer_dim(c.H, L + 1);
+    uint32_t pb = 0;
+    int pt = 0;
+    if (pin) texel_bin(P, v, L + 1, pi, pj, pb, pt);
+    const uint32_t pc = pin ? fcnt[size_t(pb) * TP + pt] : 0u;
+    const uint32_t kp = (pc & 31u) + ((pc >> 5) & 31u);
+    if (g == 0) s_pn[q] = kp;
+#pragma unroll
+    for (int r = 0; r < KEEP / 4; ++r) {
+      const uint32_t m = uint32_t(g + 4 * r);
+      if (m < kp) {
+        s_pk[m][q] = fkey[(size_t(pb) * KEEP + m) * TP + pt];
+        s_pg[m][q] = fgam[(size_t(pb) * KEEP + m) * TP + pt];
+      }
+    }
+  }
+  __syncthreads();
+  if (!in) return;  // (no later barrier)
+  const int hw = 1 << (P.ltw - 1);
+  const int q = ((j >> 1) & ((1 << (lth - 1)) - 1)) * hw + ((i >> 1) & (hw - 1));
+  const uint32_t kp = s_pn[q];
+  // stable merge of the two sorted lists, own first on equal keys
+  uint32_t io = 0, ip = 0, mask = 0;
+  uint64_t fk[KEEP];
+  float fg[KEEP];
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    const uint64_t ok = io < ko ? s_ok[min(io, uint32_t(KEEP - 1))][t] : KEY_NONE;
+    const uint64_t pk = ip < kp ? s_pk[min(ip, uint32_t(KEEP - 1))][q] : KEY_NONE;
+    const bool take_o = io < ko && !(pk < ok);
+    const bool take_p = !take_o && ip < kp;
+    fk[m] = take_o ? ok : (take_p ? pk : KEY_NONE);
+    fg[m] = take_o ? s_og[min(io, uint32_t(KEEP - 1))][t]
+                   : (take_p ? s_pg[min(ip, uint32_t(KEEP - 1))][q] : 0.0f);
+    mask |= (take_p ? 1u : 0u) << m;
+    io += take_o ? 1u : 0u;
+    ip += take_p ? 1u : 0u;
+  }
+  const uint32_t k = io + ip;
+  float C[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) C[d] = 0.0f;
+  float T = 1.0f;
+  constexpr int GB = D > 4 ? 4 : 8;
+#pragma unroll
+  for (int m0 = 0; m0 < KEEP; m0 += GB) {
+    float4 tv[GB][D / 4];
+#pragma unroll
+    for (int r = 0; r < GB; ++r) {
+      const int m = m0 + r;
+      const uint32_t id = uint32_t(m) < k ? uint32_t(fk[m]) : 0u;
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(id) * D);
+#pragma unroll
+      for (int e = 0; e < D / 4; ++e)
+        tv[r][e] = uint32_t(m) < k ? tp[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < GB; ++r) {
+      const int m = m0 + r;
+      if (uint32_t(m) < k) {
+        const float w = T * fg[m];
+#pragma unroll
+        for (int e = 0; e < D / 4; ++e) {
+          C[4 * e + 0] += w * tv[r][e].x;
+          C[4 * e + 1] += w * tv[r][e].y;
+          C[4 * e + 2] += w * tv[r][e].z;
+          C[4 * e + 3] += w * tv[r][e].w;
+        }
+        T = T * (1.0f - fg[m]);
+        fkey[(tb + m) * TP + t] = fk[m];
+        fgam[(tb + m) * TP + t] = fg[m];
+      }
+    }
+  }
+  fcnt[size_t(b) * TP + t] = io | (ip << 5) | (mask << 16);
+  write_texel<D>(C, T, size_t(c.lout[L]) + size_t(j) * WL + i, pyr, bg, alpha);
+}
+
+// incl_bwd: one launch per layer, finest first; one workgroup per tile of the layer.  Per
+// texel the blend adjoint of its blended list (as bwd_pixels) gives every item
+// dL/dgamma and T gamma G; the four finer texels it covers add what their lists passed up
+// for the items they took from it.  Each item's total then goes to the own slot it came
+// from (itot, read by the rows of the entries) or, for items of the coarser list, up to
+// the covering texel (iup, read by the next launch).  Per slot the D + 1 values are
+// (dL/dgamma, dL/dtau contribution [D]), each row of 256 texels contiguous.
+template <int D>
+__global__ __launch_bounds__(256) void k_incl_bwd(
+    const Params P, int L, const uint64_t* __restrict__ fkey, const float* __restrict__ fgam,
+    const uint32_t* __restrict__ fcnt, const float* __restrict__ desc,
+    const float* __restrict__ gpyr, float* __restrict__ itot, float* __restrict__ iup,
+    const Extras X) {
+  constexpr int S = D + 1;
+  const int v = blockIdx.y;
+  const ViewP& c = P.view[v];
+  const uint32_t local = blockIdx.x;
+  if (local >= c.lbin[L + 1] - c.lbin[L]) return;
+  const uint32_t b = c.lbin[L] + local;
+  const int t = threadIdx.x;
+  const int lth = 8 - P.ltw;
+  const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
+  const int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
+  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  const int i = (tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int j = (ty << lth) + (t >> P.ltw);
+  if (!(i < WL && j < HL)) return;
+  const size_t tb = size_t(b) * KEEP;
+  const uint32_t fc = fcnt[size_t(b) * TP + t];
+  const uint32_t k = (fc & 31u) + ((fc >> 5) & 31u);
+  const uint32_t mask = fc >> 16;
+  const size_t tex = size_t(c.lout[L]) + size_t(j) * WL + i;
+  float G[D];
+  {
+    const float4* gp = reinterpret_cast<const float4*>(gpyr + tex * D);
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q) {
+      const float4 gv = gp[q];
+      G[4 * q] = gv.x; G[4 * q + 1] = gv.y; G[4 * q + 2] = gv.z; G[4 * q + 3] = gv.w;
+    }
+  }
+  float gam[KEEP], Tm[KEEP], gm[KEEP];
+  uint32_t idx[KEEP];
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    const size_t ko = (tb + m) * TP + t;
+    const bool ok = uint32_t(m) < k;
+    idx[m] = ok ? uint32_t(fkey[ko]) : 0u;
+    gam[m] = ok ? fgam[ko] : 0.0f;
+  }
+  float T = 1.0f;
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    Tm[m] = T;
+    if (uint32_t(m) < k) T = T * (1.0f - gam[m]);
+  }
+  constexpr int GB = D > 4 ? 4 : 8;
+#pragma unroll
+  for (int m0 = 0; m0 < KEEP; m0 += GB) {
+    float4 tv[GB][D / 4];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx[m0 + q]) * D);
+#pragma unroll
+      for (int r = 0; r < D / 4; ++r)
+        tv[q][r] = uint32_t(m0 + q) < k ? tp[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
+  }
+  if (X.galpha) {
+    const float ga = X.galpha[tex];
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) gm[m] += ga;
+  }
+  float B = X.bg ? dot_g<D>(G, *reinterpret_cast<const float4(*)[D / 4]>(X.bg + tex * D)) : 0.0f;
+  float dg[KEEP], tg[KEEP];
+#pragma unroll
+  for (int m = KEEP - 1; m >= 0; --m) {
+    dg[m] = 0.0f; tg[m] = 0.0f;
+    if (uint32_t(m) < k) {
+      const float2 st = blend_adjoint_step(Tm[m], gam[m], gm[m], B);
+      dg[m] = st.x; tg[m] = st.y;
+    }
+  }
+  if (X.gbg) write_scaled<D>(X.gbg + tex * D, T, G);
+  // the finer texels this texel covers, and how many of its items each of them took
+  size_t cbase[4];
+  uint32_t cup[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cbase[q] = 0; cup[q] = 0;
+    if (L > 0) {
+      const int ci = 2 * i + (q & 1), cj = 2 * j + (q >> 1);
+      if (ci < layer_dim(c.W, L - 1) && cj < layer_dim(c.H, L - 1)) {
+        uint32_t cb;
+        int ct;
+        texel_bin(P, v, L - 1, ci, cj, cb, ct);
+        cup[q] = (fcnt[size_t(cb) * TP + ct] >> 5) & 31u;
+        cbase[q] = size_t(cb) * KEEP * S * TP + size_t(ct);
+      }
+    }
+  }
+  uint32_t so = 0, sp = 0;
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    if (uint32_t(m) < k) {
+      float tot[S];
+      tot[0] = dg[m];
+#pragma unroll
+      for (int d = 0; d < D; ++d) tot[1 + d] = tg[m] * G[d];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (uint32_t(m) < cup[q]) {
+#pragma unroll
+          for (int r = 0; r < S; ++r) tot[r] += iup[cbase[q] + (size_t(m) * S + r) * TP];
+        }
+      const bool up = (mask >> m) & 1u;
+      float* dst = up ? iup + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
+#pragma unroll
+      for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[r];
+      sp += up ? 1u : 0u;
+      so += up ? 0u : 1u;
+    }
+  }
 }
 
 // bwd_points: per point, every view: read the rows of its entries, apply the layer and
@@ -1709,10 +2013,10 @@ thread_local int32_t g_last_hip = 0;
 // launch, on the launch stream; read back and summed per stage by trips_timing_read.
 enum Stage { ST_COUNT, ST_COLSCAN, ST_BINSCAN, ST_SCATTER, ST_FWD_ITEMS,
              ST_FWD_FINE, ST_FWD_MERGE, ST_BWD_PIXELS, ST_BWD_ITEMS, ST_BWD_FINE, ST_BWD_POINTS,
-             ST_EXPORT, NUM_STAGES };
+             ST_EXPORT, ST_INCL_FWD, ST_INCL_BWD, NUM_STAGES };
 const char* const kStageNames[NUM_STAGES] = {
     "count", "colscan", "binscan", "scatter", "fwd_items", "fwd_fine", "fwd_merge",
-    "bwd_pixels", "bwd_items", "bwd_fine", "bwd_points", "export"};
+    "bwd_pixels", "bwd_items", "bwd_fine", "bwd_points", "export", "incl_fwd", "incl_bwd"};
 static_assert(NUM_STAGES == TRIPS_NUM_STAGES, "stage table");
 
 struct TimingState {
@@ -1758,10 +2062,11 @@ struct Layout {
   uint64_t npyr;      // texels of all views and layers
   // saved buffer
   size_t s_info, s_bin_start, s_item_start, s_multi, s_fine, s_coarse, s_npix, s_kkey, s_kgam,
-      s_tables_end, s_work, s_ent, s_epos;
+      s_fkey, s_fgam, s_fcnt, s_tables_end, s_work, s_ent, s_epos;
   size_t saved_bytes;
   // workspace
-  size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, ws_bytes;
+  size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, w_itot, w_iup,
+      ws_bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1796,6 +2101,9 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   Params& P = lay.P;
   P.V = views; P.nl = cfg->num_layers; P.D = cfg->desc_dim; P.ltw = ltw; P.eps = cfg->eps;
   P.pb = uint32_t(pb); P.item_e = uint32_t(item_e); P.n = n;
+  if (cfg->include_coarser != 0 && cfg->include_coarser != 1) return TRIPS_ERR_INVALID_ARG;
+  P.coarser = cfg->include_coarser;
+  P.fine_e = P.coarser ? 0u : FINE_E;
   P.nblk = uint32_t((n + pb - 1) / pb);
   const int lth = 8 - ltw;
   uint64_t bins = 0, texels = 0;
@@ -1852,6 +2160,11 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.s_npix = take(NB * TP * 4);
   lay.s_kkey = take(NB * TP * KEEP * 8);
   lay.s_kgam = take(NB * TP * KEEP * 4);
+  // coarser-layer inclusion: every texel's blended list and its make-up
+  const size_t inc = P.coarser ? 1 : 0;
+  lay.s_fkey = take(inc * NB * TP * KEEP * 8);
+  lay.s_fgam = take(inc * NB * TP * KEEP * 4);
+  lay.s_fcnt = take(inc * NB * TP * 4);
   lay.s_tables_end = o;
   // point-count dependent parts
   lay.s_work = take(size_t(lay.icap) * sizeof(uint4));
@@ -1874,6 +2187,8 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.w_bst = take(NB * TP * KEEP * sizeof(float2));
   lay.w_rows = take(size_t(views) * NSLOT * size_t(n) * (4 + P.D) * 4);
   lay.w_cam = take(size_t((n + 255) / 256) * size_t(views) * 16 * 4);
+  lay.w_itot = take(inc * NB * TP * KEEP * size_t(1 + P.D) * 4);
+  lay.w_iup = take(inc * NB * TP * KEEP * size_t(1 + P.D) * 4);
   lay.ws_bytes = std::max(fwd_end, o);
   return TRIPS_OK;
 }
@@ -1910,6 +2225,13 @@ trips_status check_points(const trips_points* pts, const Layout& lay) {
     return TRIPS_ERR_INVALID_ARG;
   if (pts->n > 0 && !aligned16(pts->desc)) return TRIPS_ERR_INVALID_ARG;
   return TRIPS_OK;
+}
+
+// Largest tile count of layer L over the views (grid width of the per-layer passes).
+uint32_t layer_tiles_max(const Params& P, int L) {
+  uint32_t m = 0;
+  for (int v = 0; v < P.V; ++v) m = std::max(m, P.view[v].lbin[L + 1] - P.view[v].lbin[L]);
+  return m;
 }
 
 template <int D>
@@ -1954,11 +2276,12 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     const uint32_t nch = (P.NB + CHUNK - 1) / CHUNK;
     uint32_t* csum = reinterpret_cast<uint32_t*>(ws + lay.w_csum);
     uint32_t* coff = reinterpret_cast<uint32_t*>(ws + lay.w_coff);
-    hipLaunchKernelGGL(k_chunksum, dim3(nch), dim3(CHUNK), 0, st, tot, csum, P.NB, P.item_e);
+    hipLaunchKernelGGL(k_chunksum, dim3(nch), dim3(CHUNK), 0, st, tot, csum, P.NB, P.item_e,
+                       P.fine_e);
     hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, st, csum, coff, bin_start, item_start,
                        info, P.NB, nch);
     hipLaunchKernelGGL(k_binscan, dim3(nch), dim3(CHUNK), 0, st, tot, coff, bin_start, item_start,
-                       multi_bins, fine_work, coarse_bins, info, work, P.NB, P.item_e);
+                       multi_bins, fine_work, coarse_bins, info, work, P.NB, P.item_e, P.fine_e);
   }
   TRIPS_HIP(hipGetLastError());
   if (P.nblk > 0) {
@@ -1991,6 +2314,18 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
                        info, pcnt, pkey, pgam, pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
   }
   TRIPS_HIP(hipGetLastError());
+  if (P.coarser) {  // coarsest layer first: each layer merges the blended lists above it
+    StageTimer tm(ST_INCL_FWD, st);
+    uint64_t* fkey = reinterpret_cast<uint64_t*>(sv + lay.s_fkey);
+    float* fgam = reinterpret_cast<float*>(sv + lay.s_fgam);
+    uint32_t* fcnt = reinterpret_cast<uint32_t*>(sv + lay.s_fcnt);
+    for (int L = P.nl - 1; L >= 0; --L) {
+      hipLaunchKernelGGL(k_incl_fwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256), 0,
+                         st, P, L, npix, kkey, kgam, fkey, fgam, fcnt, pts.desc, pyr, X.bg,
+                         X.alpha);
+      TRIPS_HIP(hipGetLastError());
+    }
+  }
   return TRIPS_OK;
 }
 
@@ -2011,24 +2346,50 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   const Entry* ent = reinterpret_cast<const Entry*>(sv + lay.s_ent);
   const uint32_t* epos = reinterpret_cast<const uint32_t*>(sv + lay.s_epos);
 
-  {
-    StageTimer tm(ST_BWD_PIXELS, st);
-    hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
-                       kkey, kgam, pts.desc, gpyr, bst, X);
+  if (P.coarser) {
+    // finest layer first: every layer's items collect what the finer lists took from them
+    // (with inclusion the fine path holds only empty tiles, so every entry is in an item)
+    const uint64_t* fkey = reinterpret_cast<const uint64_t*>(sv + lay.s_fkey);
+    const float* fgam = reinterpret_cast<const float*>(sv + lay.s_fgam);
+    const uint32_t* fcnt = reinterpret_cast<const uint32_t*>(sv + lay.s_fcnt);
+    float* itot = reinterpret_cast<float*>(ws + lay.w_itot);
+    float* iup = reinterpret_cast<float*>(ws + lay.w_iup);
+    {
+      StageTimer tm(ST_INCL_BWD, st);
+      for (int L = 0; L < P.nl; ++L) {
+        hipLaunchKernelGGL(k_incl_bwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256), 0,
+                           st, P, L, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, X);
+        TRIPS_HIP(hipGetLastError());
+      }
+    }
+    {
+      StageTimer tm(ST_BWD_ITEMS, st);
+      hipLaunchKernelGGL((k_bwd_items<D, true>), dim3(uint32_t(lay.icap) * BWD_SPLIT), dim3(256),
+                         0, st, P, info, work, ent, npix, kkey, bst, gpyr, rows, BWD_SPLIT, fcnt,
+                         itot);
+    }
+    TRIPS_HIP(hipGetLastError());
+  } else {
+    {
+      StageTimer tm(ST_BWD_PIXELS, st);
+      hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
+                         kkey, kgam, pts.desc, gpyr, bst, X);
+    }
+    TRIPS_HIP(hipGetLastError());
+    {
+      StageTimer tm(ST_BWD_ITEMS, st);
+      hipLaunchKernelGGL((k_bwd_items<D, false>), dim3(uint32_t(lay.icap) * BWD_SPLIT), dim3(256),
+                         0, st, P, info, work, ent, npix, kkey, bst, gpyr, rows, BWD_SPLIT,
+                         nullptr, nullptr);
+    }
+    TRIPS_HIP(hipGetLastError());
+    {
+      StageTimer tm(ST_BWD_FINE, st);
+      hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent, npix,
+                         pts.desc, gpyr, rows, X);
+    }
+    TRIPS_HIP(hipGetLastError());
   }
-  TRIPS_HIP(hipGetLastError());
-  {
-    StageTimer tm(ST_BWD_ITEMS, st);
-    hipLaunchKernelGGL(k_bwd_items<D>, dim3(uint32_t(lay.icap) * BWD_SPLIT), dim3(256), 0, st, P,
-                       info, work, ent, npix, kkey, bst, gpyr, rows, BWD_SPLIT);
-  }
-  TRIPS_HIP(hipGetLastError());
-  {
-    StageTimer tm(ST_BWD_FINE, st);
-    hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent, npix,
-                       pts.desc, gpyr, rows, X);
-  }
-  TRIPS_HIP(hipGetLastError());
   if (P.n > 0) {
     StageTimer tm(ST_BWD_POINTS, st);
     const uint32_t nblk = uint32_t((P.n + 255) / 256);
@@ -2206,7 +2567,9 @@ trips_status trips_export_fragments(const trips_config* cfg, const trips_camera*
     StageTimer tm(ST_EXPORT, st);
     hipLaunchKernelGGL(k_export, dim3(lay.P.NB), dim3(256), 0, st, lay.P,
                        reinterpret_cast<const uint32_t*>(sv + lay.s_npix),
-                       reinterpret_cast<const uint64_t*>(sv + lay.s_kkey), counts, ids);
+                       reinterpret_cast<const uint64_t*>(sv + lay.s_kkey),
+                       reinterpret_cast<const uint64_t*>(sv + lay.s_fkey),
+                       reinterpret_cast<const uint32_t*>(sv + lay.s_fcnt), counts, ids);
     TRIPS_HIP(hipGetLastError());
   }
   return TRIPS_OK;

@@ -18,11 +18,11 @@ def to_device(pts, dev):
     return {k: torch.from_numpy(np.ascontiguousarray(pts[k])).to(dev) for k in PARAMS}
 
 
-def renderer(sc, dev, tuning=None, cams=None):
+def renderer(sc, dev, tuning=None, cams=None, include_coarser=False):
     import paper_2401_06003_amd as tp
     cams = sc["cams"] if cams is None else cams
     return tp.Renderer(cams, sc["nlayers"], sc["D"], len(sc["points"]["x"]), tuning=tuning,
-                       device=dev)
+                       device=dev, include_coarser=include_coarser)
 
 
 def gpu_forward(sc, dev, tuning=None, cams=None):

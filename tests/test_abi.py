@@ -66,6 +66,28 @@ def test_invalid_arguments(cfg, views, n, tune, code):
     assert st == code
 
 
+def test_inclusion_flag_sizes_and_range():
+    tp, L = _lib()
+    cams = (tp.Camera * 1)(tp.make_camera(_cam(64, 48)))
+    sizes = []
+    for flag in (0, 1):
+        ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+        cfg = tp.make_config(5, 4, include_coarser=flag)
+        assert L.trips_buffer_sizes(ctypes.byref(cfg), cams, 1, 1000, None, ctypes.byref(ws),
+                                    ctypes.byref(sv)) == 0
+        sizes.append((ws.value, sv.value))
+    # 4 x 3 + 2 x 2 + 1 + 1 + 1 = 19 tiles of 16x16 over the 64x48 pyramid of 5 layers;
+    # inclusion keeps 16 keys, gammas and a count per texel and two (1 + D)-float tables
+    tiles = 19
+    assert sizes[1][1] - sizes[0][1] >= tiles * 256 * (16 * 12 + 4)
+    assert sizes[1][0] > sizes[0][0] and sizes[1][0] >= tiles * 256 * 16 * 5 * 4 * 2
+    bad = tp.make_config(5, 4)
+    bad.include_coarser = 2
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.trips_buffer_sizes(ctypes.byref(bad), cams, 1, 1000, None, ctypes.byref(ws),
+                                ctypes.byref(sv)) == -1
+
+
 def test_bad_camera_rejected():
     tp, L = _lib()
     c = _cam(64, 48)

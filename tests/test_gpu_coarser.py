@@ -1,0 +1,202 @@
+"""GPU parity of coarser-layer inclusion (Sec. 3.2) through the C ABI: every texel blends its
+own fragments together with those of the coarser layers' texels that cover it.  Compared
+with the oracle's inclusion mode on the same seeded inputs (blended lists exactly; pyramid,
+coverage and gradients within the single-precision bars), with batched views equal to
+per-view calls and captured plans equal to eager calls bit for bit."""
+import numpy as np
+import pytest
+
+import scenes
+from gpu_util import GRAD_KEY, PARAMS, assert_lists, assert_pyramid, grad_close, renderer, to_device
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+ALPHA_ATOL = 1e-5
+
+
+def _inputs(P, D, seed):
+    rng = np.random.default_rng(seed)
+    bg = rng.uniform(0.0, 1.0, (P, D)).astype(np.float32)
+    G = scenes.upstream_gradient(seed, P * D).reshape(P, D).astype(np.float32)
+    Ga = rng.standard_normal(P).astype(np.float32)
+    return bg, G, Ga
+
+
+def _gpu(sc, dev, bg, G, Ga, tuning=None, cams=None):
+    import torch
+    r = renderer(sc, dev, tuning, cams, include_coarser=True)
+    t = to_device(sc["points"], dev)
+    args = [t[k] for k in PARAMS]
+    P, D = r.texels, sc["D"]
+    bgt = torch.from_numpy(np.ascontiguousarray(bg).reshape(-1)).to(dev)
+    alpha = torch.empty(P, device=dev)
+    pyr = r.forward(*args, background=bgt, alpha_out=alpha)
+    counts, ids = r.export_fragments()
+    g = torch.from_numpy(np.ascontiguousarray(G).reshape(-1)).to(dev)
+    ga = torch.from_numpy(np.ascontiguousarray(Ga)).to(dev)
+    gbg = torch.empty(P * D, device=dev)
+    gcam = torch.empty((r.V, 16), device=dev)
+    outs = r.backward(*args, g, background=bgt, grad_alpha=ga, grad_background=gbg,
+                      grad_camera=gcam)
+    torch.cuda.synchronize()
+    res = {"pyr": pyr.cpu().numpy().astype(np.float64).reshape(P, D),
+           "coverage": alpha.cpu().numpy().astype(np.float64), "counts": counts.cpu().numpy(),
+           "ids": ids.cpu().numpy().astype(np.int64),
+           "gbg": gbg.cpu().numpy().astype(np.float64).reshape(P, D),
+           "gcam": gcam.cpu().numpy().astype(np.float64)}
+    for k, o in zip(PARAMS, outs):
+        res[k] = o.cpu().numpy().astype(np.float64)
+    return res
+
+
+def _check_view(got, sc, cam, bg, G, Ga, mask=None, where=""):
+    nl = sc["nlayers"]
+    f = oracle.forward_ex(sc["points"], cam, nl, background=bg.astype(np.float64), coarser=True,
+                          mask=mask)
+    sel = slice(None) if mask is None else mask.astype(bool)
+    assert_lists(got["counts"][sel], got["ids"][sel], f["counts"][sel], f["ids"][sel], where)
+    assert_pyramid(got["pyr"][sel], f["pyr"][sel], where)
+    assert np.abs(got["coverage"][sel] - f["alpha"][sel]).max() <= ALPHA_ATOL, where
+    b = oracle.backward_ex(sc["points"], cam, nl, G.astype(np.float64),
+                           background=bg.astype(np.float64), grad_alpha=Ga.astype(np.float64),
+                           coarser=True, mask=mask)
+    for k in PARAMS:
+        grad_close(got[k], b[GRAD_KEY[k]].reshape(got[k].shape), where + k)
+    grad_close(got["gbg"][sel], b["gbg"][sel], where + "gbg")
+    grad_close(got["gcam"].reshape(-1), b["gcam"], where + "gcam", rtol_norm=1e-4, rtol=1e-2,
+               atol_rel=1e-4)
+    return f
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("tile_w", [8, 16, 64])
+def test_small_scenes(gpu, seed, tile_w):
+    import paper_2401_06003_amd as tp
+    sc = scenes.random_small(500 + seed, n=600, W=90, H=70, nlayers=5, s_lo=0.3, s_hi=24.0)
+    cam = sc["cams"][0]
+    P = oracle.num_pixels(cam["W"], cam["H"], sc["nlayers"])
+    bg, G, Ga = _inputs(P, sc["D"], seed + 70)
+    got = _gpu(sc, gpu, bg, G, Ga, tp.make_tuning(tile_w, 0, 0))
+    got["gcam"] = got["gcam"][0]
+    f = _check_view(got, sc, cam, bg, G, Ga)
+    # inclusion is exercised: lists that take in coarser fragments, and full lists
+    plain = oracle.forward_ex(sc["points"], cam, sc["nlayers"])
+    assert (f["ids"] != plain["ids"]).any(axis=1).sum() > 100
+    assert (f["ids"][:, -1] >= 0).sum() > 0
+
+
+def test_depth_ties_and_single_layer(gpu):
+    """Equal depths across points (index ties) and a point meeting itself across layers;
+    with one layer inclusion changes nothing."""
+    for nl in (1, 4):
+        sc = scenes.random_small(510, n=700, W=48, H=40, nlayers=nl, depth_ties=True)
+        cam = sc["cams"][0]
+        P = oracle.num_pixels(cam["W"], cam["H"], nl)
+        bg, G, Ga = _inputs(P, sc["D"], 80 + nl)
+        got = _gpu(sc, gpu, bg, G, Ga)
+        got["gcam"] = got["gcam"][0]
+        _check_view(got, sc, cam, bg, G, Ga, where="layers %d " % nl)
+
+
+def test_heavy_lists_items(gpu):
+    """Long lists cut into several work items (partial lists merged) before inclusion."""
+    import paper_2401_06003_amd as tp
+    sc = scenes.random_small(511, n=5000, W=40, H=30, nlayers=4, s_lo=2.0, s_hi=12.0)
+    cam = sc["cams"][0]
+    P = oracle.num_pixels(cam["W"], cam["H"], sc["nlayers"])
+    bg, G, Ga = _inputs(P, sc["D"], 90)
+    got = _gpu(sc, gpu, bg, G, Ga, tp.make_tuning(16, 256, 256))
+    got["gcam"] = got["gcam"][0]
+    _check_view(got, sc, cam, bg, G, Ga)
+
+
+def test_descriptor_width_8(gpu):
+    sc = scenes.unit_cube(6, n=2000, W=120, H=90, nlayers=5, D=8)
+    cam = sc["cams"][0]
+    P = oracle.num_pixels(cam["W"], cam["H"], sc["nlayers"])
+    bg, G, Ga = _inputs(P, 8, 91)
+    got = _gpu(sc, gpu, bg, G, Ga)
+    got["gcam"] = got["gcam"][0]
+    _check_view(got, sc, cam, bg, G, Ga)
+
+
+def _three_cams(sc):
+    c0 = sc["cams"][0]
+    c1 = dict(c0, t=np.asarray(c0["t"], dtype=np.float64) + np.array([0.05, -0.03, 0.1]))
+    c2 = scenes.camera(np.eye(3), (0.02, 0.01, 0.0), 64, 48, 50.0)
+    return [c0, c1, c2]
+
+
+def test_batched_equals_per_view_bitwise(gpu):
+    sc = scenes.random_small(512, n=800, W=80, H=60, nlayers=5, s_lo=0.3, s_hi=20.0)
+    cams = _three_cams(sc)
+    Ps = [oracle.num_pixels(c["W"], c["H"], sc["nlayers"]) for c in cams]
+    ins = [_inputs(P, sc["D"], 100 + v) for v, P in enumerate(Ps)]
+    bg = np.concatenate([i[0] for i in ins])
+    G = np.concatenate([i[1] for i in ins])
+    Ga = np.concatenate([i[2] for i in ins])
+    batched = _gpu(sc, gpu, bg, G, Ga, cams=cams)
+    total = {k: 0.0 for k in PARAMS}
+    o = 0
+    for v, (c, P) in enumerate(zip(cams, Ps)):
+        one = _gpu(sc, gpu, ins[v][0], ins[v][1], ins[v][2], cams=[c])
+        for k in ("pyr", "coverage", "gbg", "counts", "ids"):
+            assert np.array_equal(batched[k][o:o + P], one[k]), (v, k)
+        assert np.array_equal(batched["gcam"][v], one["gcam"][0]), v
+        for k in PARAMS:
+            total[k] = total[k] + one[k]
+        o += P
+    for k in PARAMS:  # per-view gradients summed (in another order than the batched sum)
+        grad_close(batched[k], total[k], "sum " + k, rtol_norm=1e-5, rtol=1e-4, atol_rel=1e-6)
+
+
+def test_plan_replays_equal_eager(gpu):
+    import torch
+    import paper_2401_06003_amd as tp
+    sc = scenes.random_small(513, n=600, W=70, H=50, nlayers=5)
+    cams = _three_cams(sc)[:2]
+    r = renderer(sc, gpu, cams=cams, include_coarser=True)
+    t = to_device(sc["points"], gpu)
+    args = [t[k] for k in PARAMS]
+    P, D, n = r.texels, sc["D"], len(sc["points"]["x"])
+    bg, G, Ga = (torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(gpu)
+                 for a in _inputs(P, D, 110))
+    eager_alpha = torch.empty(P, device=gpu)
+    eager_pyr = r.forward(*args, background=bg, alpha_out=eager_alpha).clone()
+    eg = torch.empty(P * D, device=gpu)
+    ec = torch.empty((2, 16), device=gpu)
+    eager = [o.clone() for o in r.backward(*args, G, background=bg, grad_alpha=Ga,
+                                           grad_background=eg, grad_camera=ec)]
+    pyr = torch.empty(P * D, device=gpu)
+    alpha = torch.empty(P, device=gpu)
+    gbg = torch.empty(P * D, device=gpu)
+    gcam = torch.empty((2, 16), device=gpu)
+    grads = [torch.empty(n, device=gpu) for _ in range(5)] + [torch.empty((n, D), device=gpu)]
+    plan = tp.Plan(r, *args, pyr, G, grads, background=bg, alpha_out=alpha, grad_alpha=Ga,
+                   grad_background=gbg, grad_camera=gcam)
+    for _ in range(3):
+        for x in (pyr, alpha, gbg, gcam, *grads):
+            x.fill_(-7.0)
+        plan.launch(forward=True, backward=True)
+        torch.cuda.synchronize()
+        assert torch.equal(pyr, eager_pyr) and torch.equal(alpha, eager_alpha)
+        assert torch.equal(gbg, eg) and torch.equal(gcam, ec)
+        for a, b in zip(grads, eager):
+            assert torch.equal(a, b)
+
+
+def test_full_size_sampled_texels(gpu):
+    """The 2M-point 1080p scene: a random 0.3% of the texels (with G, the coverage gradient
+    and the background zero elsewhere) against the oracle evaluated on those texels, which
+    makes every point gradient exact."""
+    sc = scenes.cluster_scene(2)
+    cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
+    P = oracle.num_pixels(cam["W"], cam["H"], nl)
+    bg, G, Ga = _inputs(P, D, 120)
+    mask = (np.random.default_rng(121).random(P) < 0.003).astype(np.uint8)
+    G = G * mask[:, None]
+    Ga = Ga * mask
+    got = _gpu(sc, gpu, bg, G, Ga)
+    got["gcam"] = got["gcam"][0]
+    _check_view(got, sc, cam, bg, G, Ga, mask=mask, where="full size ")
