@@ -1,6 +1,7 @@
 """Benchmark: splatted points per second for forward+backward trilinear point splatting.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
+                [--no-coarser]
 
 Workload (one step = the whole hot path once): 2M points drawn from 64 anisotropic Gaussian
 clusters plus 30% on planar patches, one 1920x1080 pinhole view, 8 pyramid layers,
@@ -14,7 +15,8 @@ replayed (the eager launch sequence is timed as well).  Also reported: per-kerne
 (a second timed run of eager steps with HIP events around every launch, on its stream), the
 roofline of the dominant kernel, the CPU oracle on the same workload, and the batched
 multi-view form (16 views of mixed resolution over 4M points, one graph launch per step)
-against 16 single-view launch sequences.
+against 16 single-view launch sequences, and the same workload with coarser-layer
+inclusion in blending.
 """
 import argparse
 import json
@@ -104,6 +106,51 @@ def cpu_baseline(sc, G):
                       "single thread, %.1f s" % (n, cam["W"], cam["H"], nl, dt)}
 
 
+def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev):
+    """The headline workload with coarser-layer inclusion: graph-replayed steps, then eager
+    steps with per-kernel events.  The inclusion passes are charged their algorithmic bytes:
+    forward, per texel the own kept fragments read (12 B), every blended item written and
+    its descriptor gathered (12 + 4D B) plus the texel (4D B) and its count (4 B); backward,
+    every blended item read with its descriptor (12 + 4D B) and its totals written and read
+    once more (8 (1 + D) B), plus the upstream gradient (4D B) and the count (4 B)."""
+    cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
+    N = len(sc["points"]["x"])
+    r = tp.Renderer([cam], nl, D, N, device=dev, include_coarser=True)
+    pyr = torch.empty(r.pyramid_numel(), device=dev)
+    grads = [torch.empty(N, device=dev) for _ in range(5)] + [torch.empty((N, D), device=dev)]
+    plan = tp.Plan(r, *pargs, pyr, G, grads)
+    for _ in range(warmup):
+        plan.launch(forward=True, backward=True)
+    torch.cuda.synchronize()
+    counts, ids = r.export_fragments()
+    c64 = counts.to(torch.int64)
+    K = int(torch.clamp(c64, max=tp.KEEP).sum().item())
+    Fb = int((ids >= 0).sum().item())
+    P = r.texels
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.launch(forward=True, backward=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tp.timing_enable(True)
+    for _ in range(steps):
+        r.forward(*pargs, out=pyr)
+        r.backward(*pargs, G, outs=grads)
+    torch.cuda.synchronize()
+    stages = tp.timing_read()
+    tp.timing_enable(False)
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1] > 0}
+    ib = {"incl_fwd": 12 * K + (12 + 4 * D) * Fb + (4 * D + 4) * P,
+          "incl_bwd": (12 + 4 * D + 8 * (1 + D)) * Fb + (4 * D + 4) * P}
+    return {"workload": "clusters2m_1920x1080_8layers_d4_fwd_bwd_coarser_inclusion",
+            "ms_per_step": ms, "points_per_s": N / (ms / 1e3), "blended_items": Fb,
+            "blended_items_plain": K, "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+            "incl_gbps": {k: round(b / (stage_ms[k] / 1e3) / 1e9, 1) for k, b in ib.items()
+                          if k in stage_ms}}
+
+
 def run_batched(torch, tp, scenes, steps, warmup, dev):
     """16 views of mixed resolution over 4M points: one graph launch per step vs 16
     single-view forward+backward sequences on the same stream."""
@@ -161,6 +208,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-coarser", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference for "
                          "scaling HBM byte counters) and exit")
@@ -280,6 +328,9 @@ def main():
         "stage_gbps": {k: round(kernel_bytes(k, w) / (v / 1e3) / 1e9, 1)
                        for k, v in stage_ms.items() if kernel_bytes(k, w)},
     }
+    if not args.no_coarser:
+        log("coarser-layer inclusion on the same workload")
+        out["coarser"] = run_coarser(torch, tp, sc, pargs, G, args.steps, args.warmup, dev)
     if not args.no_batched:
         log("batched vs per-view (16 views, 4M points)")
         out["batched"] = run_batched(torch, tp, scenes, max(3, args.steps // 4),

@@ -60,7 +60,7 @@ typedef struct {
 
 /* Renderer hyper-parameters (Sec. 3.1-3.2).
    include_coarser (0 or 1; zero-initialised configs leave it off): coarser-layer inclusion
-   of Sec. 3.2.  The list blended at texel (i, j) of layer L then holds, besides the
+   of Sec. 3.6.  The list blended at texel (i, j) of layer L then holds, besides the
    texel's own fragments, the fragments of texel (i >> k, j >> k) of every coarser layer
    L + k, each with its own gamma; the union is ordered by depth, point index, then layer
    (finer first; a point written to two layers can appear twice) and clamped to

@@ -17,7 +17,7 @@
  *      each fragment carries gamma = beta * iota * alpha (Eq. 3).
  *   4. Collect the fragments of every (layer, pixel), sort them by depth (ties by
  *      point index) and keep the front-most 16 (Sec. 3.2).  Optionally (coarser-layer
- *      inclusion, Sec. 3.2) the list of a texel also holds the fragments of the texels of
+ *      inclusion, Sec. 3.6) the list of a texel also holds the fragments of the texels of
  *      all coarser layers that cover it.
  *   5. Blend front to back, C = sum_m T_m gamma_m tau_m with
  *      T_m = prod_{i<m} (1 - gamma_i) (Eq. 6-7).
@@ -285,7 +285,7 @@ static int64_t* texel_runs(const frag_t* fr, int64_t nf, int64_t P) {
   return run;
 }
 
-/* Coarser-layer inclusion (Sec. 3.2, last paragraph): texel (i, j) of layer L also blends
+/* Coarser-layer inclusion (Sec. 3.6): texel (i, j) of layer L also blends
    the fragments of the texel (i >> k, j >> k) of every coarser layer L + k, the texel of
    that layer that covers it.  Returns the list of texel pix in blend order (own fragments
    alone without inclusion); buf has room for every fragment. */

@@ -177,7 +177,7 @@ class Renderer:
     """Renders one or more views (different resolutions allowed) of a point cloud.
 
     Owns the `saved` and `workspace` device buffers (torch tensors) sized by the library.
-    include_coarser: coarser-layer inclusion (Sec. 3.2): every texel also blends the
+    include_coarser: coarser-layer inclusion (Sec. 3.6): every texel also blends the
     fragments of the coarser layers' texels that cover it."""
 
     def __init__(self, cams, num_layers, desc_dim, n_points, eps=0.25, tuning=None,

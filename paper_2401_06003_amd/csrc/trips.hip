@@ -1583,7 +1583,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // ------------------------------------------------------------------------------------
-// Coarser-layer inclusion (Sec. 3.2).  The list blended at texel (i, j) of layer L is the
+// Coarser-layer inclusion (Sec. 3.6).  The list blended at texel (i, j) of layer L is the
 // texel's own kept list merged with the blended list of the covering texel (i/2, j/2) of
 // layer L + 1, which by induction holds the fragments of every coarser layer: the 16
 // smallest of a union are the 16 smallest of the union of the parts' 16 smallest.  The

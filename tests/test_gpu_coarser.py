@@ -1,4 +1,4 @@
-"""GPU parity of coarser-layer inclusion (Sec. 3.2) through the C ABI: every texel blends its
+"""GPU parity of coarser-layer inclusion (Sec. 3.6) through the C ABI: every texel blends its
 own fragments together with those of the coarser layers' texels that cover it.  Compared
 with the oracle's inclusion mode on the same seeded inputs (blended lists exactly; pyramid,
 coverage and gradients within the single-precision bars), with batched views equal to

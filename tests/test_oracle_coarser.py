@@ -1,4 +1,4 @@
-"""Pins of the oracle's coarser-layer inclusion (Sec. 3.2, last paragraph): the list a texel
+"""Pins of the oracle's coarser-layer inclusion (Sec. 3.6): the list a texel
 blends also holds the fragments of the texels of every coarser layer that cover it.
 
 The paper gives the rule no more detail than that it is done the usual way; the reading
