@@ -630,6 +630,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
     const float xn = X[pc], yn = Y[pc], zn = Z[pc], swn = SW[pc], aln = A[pc];
     const float alpha = al;
     bool any = false;
+    uint32_t er[NSLOT];  // the point's entry positions, written as one 32-byte record
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) er[k] = 0u;
     for_each_entry(P, c, x, y, z, sw,
                    [&](uint32_t bin, uint32_t slot, int sel, const Foot& ft, const Geo& g) {
                      any = true;
@@ -644,9 +647,14 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
                      e.slot = slot;
                      const uint32_t at = (STAGED ? base[lb] : bs[lb] + row[lb]) + rank;
                      ent[at] = e;
-                     // where the backward finds this entry's row
-                     epos[(size_t(v) * NSLOT + slot) * size_t(P.n) + size_t(p)] = at;
+#pragma unroll
+                     for (int k = 0; k < NSLOT; ++k) er[k] = slot == uint32_t(k) ? at : er[k];
                    });
+    if (any) {  // where the backward finds the rows of this point's entries
+      uint4* ep4 = reinterpret_cast<uint4*>(epos + (size_t(v) * size_t(P.n) + size_t(p)) * NSLOT);
+      ep4[0] = make_uint4(er[0], er[1], er[2], er[3]);
+      ep4[1] = make_uint4(er[4], er[5], er[6], er[7]);
+    }
     vis += any ? 1u : 0u;
     x = xn; y = yn; z = zn; sw = swn; al = aln;
   }
@@ -1637,21 +1645,29 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
   const size_t tb = size_t(b) * KEEP;
   const uint32_t ko = in ? min(npix[size_t(b) * TP + t], uint32_t(KEEP)) : 0u;
   if (L == P.nl - 1) {  // uniform: the coarsest layer blends its own list (already written)
+    uint64_t ck[KEEP];
+    float cg[KEEP];
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) {
+      ck[m] = kkey[(tb + m) * TP + t];
+      cg[m] = kgam[(tb + m) * TP + t];
+    }
 #pragma unroll
     for (int m = 0; m < KEEP; ++m)
       if (uint32_t(m) < ko) {
-        fkey[(tb + m) * TP + t] = kkey[(tb + m) * TP + t];
-        fgam[(tb + m) * TP + t] = kgam[(tb + m) * TP + t];
+        fkey[(tb + m) * TP + t] = ck[m];
+        fgam[(tb + m) * TP + t] = cg[m];
       }
     fcnt[size_t(b) * TP + t] = ko;
     return;
   }
+  // all 16 slots are staged (slots past the list hold stale values and are never read), so
+  // the loads do not wait on one another
 #pragma unroll
-  for (int m = 0; m < KEEP; ++m)
-    if (uint32_t(m) < ko) {
-      s_ok[m][t] = kkey[(tb + m) * TP + t];
-      s_og[m][t] = kgam[(tb + m) * TP + t];
-    }
+  for (int m = 0; m < KEEP; ++m) {
+    s_ok[m][t] = kkey[(tb + m) * TP + t];
+    s_og[m][t] = kgam[(tb + m) * TP + t];
+  }
   {  // the covering texels: (tw/2) x (th/2) texels of one tile of layer L + 1
     const int hw = 1 << (P.ltw - 1);
     const int q = t & (PT - 1), g = t >> 6;  // texel q, slots g, g+4, g+8, g+12
@@ -1667,10 +1683,8 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
 #pragma unroll
     for (int r = 0; r < KEEP / 4; ++r) {
       const uint32_t m = uint32_t(g + 4 * r);
-      if (m < kp) {
-        s_pk[m][q] = fkey[(size_t(pb) * KEEP + m) * TP + pt];
-        s_pg[m][q] = fgam[(size_t(pb) * KEEP + m) * TP + pt];
-      }
+      s_pk[m][q] = fkey[(size_t(pb) * KEEP + m) * TP + pt];
+      s_pg[m][q] = fgam[(size_t(pb) * KEEP + m) * TP + pt];
     }
   }
   __syncthreads();
@@ -1703,6 +1717,7 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
   constexpr int GB = D > 4 ? 4 : 8;
 #pragma unroll
   for (int m0 = 0; m0 < KEEP; m0 += GB) {
+    // a batch of descriptor gathers, all issued before use (an empty slot reads point 0)
     float4 tv[GB][D / 4];
 #pragma unroll
     for (int r = 0; r < GB; ++r) {
@@ -1710,8 +1725,7 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
       const uint32_t id = uint32_t(m) < k ? uint32_t(fk[m]) : 0u;
       const float4* tp = reinterpret_cast<const float4*>(desc + size_t(id) * D);
 #pragma unroll
-      for (int e = 0; e < D / 4; ++e)
-        tv[r][e] = uint32_t(m) < k ? tp[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int e = 0; e < D / 4; ++e) tv[r][e] = tp[e];
     }
 #pragma unroll
     for (int r = 0; r < GB; ++r) {
@@ -1726,13 +1740,86 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
           C[4 * e + 3] += w * tv[r][e].w;
         }
         T = T * (1.0f - fg[m]);
-        fkey[(tb + m) * TP + t] = fk[m];
-        fgam[(tb + m) * TP + t] = fg[m];
       }
     }
   }
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m)
+    if (uint32_t(m) < k) {
+      fkey[(tb + m) * TP + t] = fk[m];
+      fgam[(tb + m) * TP + t] = fg[m];
+    }
   fcnt[size_t(b) * TP + t] = io | (ip << 5) | (mask << 16);
   write_texel<D>(C, T, size_t(c.lout[L]) + size_t(j) * WL + i, pyr, bg, alpha);
+}
+
+// Blend adjoint of the blended list of one texel (tile b, slot t, pyramid texel tex; fc its
+// count word): G, and per item m < k dg[m] = dL/dgamma_m and tg[m] = T_m gamma_m (zero past
+// k); writes the background gradient.  Returns k.
+template <int D>
+__device__ __forceinline__ uint32_t blended_adjoint(const uint64_t* __restrict__ fkey,
+                                                    const float* __restrict__ fgam, uint32_t b,
+                                                    int t, uint32_t fc, size_t tex,
+                                                    const float* __restrict__ desc,
+                                                    const float* __restrict__ gpyr, const Extras& X,
+                                                    float (&G)[D], float (&dg)[KEEP],
+                                                    float (&tg)[KEEP]) {
+  const size_t tb = size_t(b) * KEEP;
+  const uint32_t k = (fc & 31u) + ((fc >> 5) & 31u);
+  {
+    const float4* gp = reinterpret_cast<const float4*>(gpyr + tex * D);
+#pragma unroll
+    for (int q = 0; q < D / 4; ++q) {
+      const float4 gv = gp[q];
+      G[4 * q] = gv.x; G[4 * q + 1] = gv.y; G[4 * q + 2] = gv.z; G[4 * q + 3] = gv.w;
+    }
+  }
+  float gam[KEEP], Tm[KEEP], gm[KEEP];
+  uint32_t idx[KEEP];
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {  // every slot is read (in bounds), those past k dropped
+    const size_t ko = (tb + m) * TP + t;
+    const uint64_t kr = fkey[ko];
+    const float gr = fgam[ko];
+    const bool ok = uint32_t(m) < k;
+    idx[m] = ok ? uint32_t(kr) : 0u;
+    gam[m] = ok ? gr : 0.0f;
+  }
+  float T = 1.0f;
+#pragma unroll
+  for (int m = 0; m < KEEP; ++m) {
+    Tm[m] = T;
+    if (uint32_t(m) < k) T = T * (1.0f - gam[m]);
+  }
+  constexpr int GB = D > 4 ? 4 : 8;
+#pragma unroll
+  for (int m0 = 0; m0 < KEEP; m0 += GB) {
+    float4 tv[GB][D / 4];  // empty slots read point 0 and are dropped
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx[m0 + q]) * D);
+#pragma unroll
+      for (int r = 0; r < D / 4; ++r) tv[q][r] = tp[r];
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
+  }
+  if (X.galpha) {
+    const float ga = X.galpha[tex];
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) gm[m] += ga;
+  }
+  float B = X.bg ? dot_g<D>(G, *reinterpret_cast<const float4(*)[D / 4]>(X.bg + tex * D)) : 0.0f;
+#pragma unroll
+  for (int m = KEEP - 1; m >= 0; --m) {
+    dg[m] = 0.0f; tg[m] = 0.0f;
+    if (uint32_t(m) < k) {
+      const float2 st = blend_adjoint_step(Tm[m], gam[m], gm[m], B);
+      dg[m] = st.x; tg[m] = st.y;
+    }
+  }
+  if (X.gbg) write_scaled<D>(X.gbg + tex * D, T, G);
+  return k;
 }
 
 // incl_bwd: one launch per layer, finest first; one workgroup per tile of the layer.  Per
@@ -1746,8 +1833,10 @@ template <int D>
 __global__ __launch_bounds__(256) void k_incl_bwd(
     const Params P, int L, const uint64_t* __restrict__ fkey, const float* __restrict__ fgam,
     const uint32_t* __restrict__ fcnt, const float* __restrict__ desc,
-    const float* __restrict__ gpyr, float* __restrict__ itot, float* __restrict__ iup,
-    const Extras X) {
+    const float* __restrict__ gpyr, float* __restrict__ itot, const float* __restrict__ iup_in,
+    float* __restrict__ iup_out, const Extras X) {
+  // iup_in and iup_out are the same table: this launch reads the rows of layer L - 1 and
+  // writes those of layer L, which never overlap
   constexpr int S = D + 1;
   const int v = blockIdx.y;
   const ViewP& c = P.view[v];
@@ -1764,63 +1853,10 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   if (!(i < WL && j < HL)) return;
   const size_t tb = size_t(b) * KEEP;
   const uint32_t fc = fcnt[size_t(b) * TP + t];
-  const uint32_t k = (fc & 31u) + ((fc >> 5) & 31u);
   const uint32_t mask = fc >> 16;
   const size_t tex = size_t(c.lout[L]) + size_t(j) * WL + i;
-  float G[D];
-  {
-    const float4* gp = reinterpret_cast<const float4*>(gpyr + tex * D);
-#pragma unroll
-    for (int q = 0; q < D / 4; ++q) {
-      const float4 gv = gp[q];
-      G[4 * q] = gv.x; G[4 * q + 1] = gv.y; G[4 * q + 2] = gv.z; G[4 * q + 3] = gv.w;
-    }
-  }
-  float gam[KEEP], Tm[KEEP], gm[KEEP];
-  uint32_t idx[KEEP];
-#pragma unroll
-  for (int m = 0; m < KEEP; ++m) {
-    const size_t ko = (tb + m) * TP + t;
-    const bool ok = uint32_t(m) < k;
-    idx[m] = ok ? uint32_t(fkey[ko]) : 0u;
-    gam[m] = ok ? fgam[ko] : 0.0f;
-  }
-  float T = 1.0f;
-#pragma unroll
-  for (int m = 0; m < KEEP; ++m) {
-    Tm[m] = T;
-    if (uint32_t(m) < k) T = T * (1.0f - gam[m]);
-  }
-  constexpr int GB = D > 4 ? 4 : 8;
-#pragma unroll
-  for (int m0 = 0; m0 < KEEP; m0 += GB) {
-    float4 tv[GB][D / 4];
-#pragma unroll
-    for (int q = 0; q < GB; ++q) {
-      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx[m0 + q]) * D);
-#pragma unroll
-      for (int r = 0; r < D / 4; ++r)
-        tv[q][r] = uint32_t(m0 + q) < k ? tp[r] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll
-    for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
-  }
-  if (X.galpha) {
-    const float ga = X.galpha[tex];
-#pragma unroll
-    for (int m = 0; m < KEEP; ++m) gm[m] += ga;
-  }
-  float B = X.bg ? dot_g<D>(G, *reinterpret_cast<const float4(*)[D / 4]>(X.bg + tex * D)) : 0.0f;
-  float dg[KEEP], tg[KEEP];
-#pragma unroll
-  for (int m = KEEP - 1; m >= 0; --m) {
-    dg[m] = 0.0f; tg[m] = 0.0f;
-    if (uint32_t(m) < k) {
-      const float2 st = blend_adjoint_step(Tm[m], gam[m], gm[m], B);
-      dg[m] = st.x; tg[m] = st.y;
-    }
-  }
-  if (X.gbg) write_scaled<D>(X.gbg + tex * D, T, G);
+  float G[D], dg[KEEP], tg[KEEP];
+  const uint32_t k = blended_adjoint<D>(fkey, fgam, b, t, fc, tex, desc, gpyr, X, G, dg, tg);
   // the finer texels this texel covers, and how many of its items each of them took
   size_t cbase[4];
   uint32_t cup[4];
@@ -1838,24 +1874,138 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
       }
     }
   }
+  // every item's total: its blend part, then what each finer texel passed up (in child
+  // order); all loads of a half list are issued before any store
+  uint32_t so = 0, sp = 0;
+  constexpr int H = D > 4 ? KEEP / 4 : KEEP / 2;
+#pragma unroll
+  for (int h = 0; h < KEEP; h += H) {
+    float tot[H][S];
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      tot[m][0] = dg[h + m];
+#pragma unroll
+      for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[h + m] * G[d];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        // read whatever the slot holds (in bounds: a missing child reads tile 0), use it
+        // only for the items that child took
+        const bool take = uint32_t(h + m) < cup[q];
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+          const float u = iup_in[cbase[q] + (size_t(h + m) * S + r) * TP];
+          tot[m][r] += take ? u : 0.0f;
+        }
+      }
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      if (uint32_t(h + m) < k) {
+        const bool up = (mask >> (h + m)) & 1u;
+        float* dst = up ? iup_out + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
+#pragma unroll
+        for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
+        sp += up ? 1u : 0u;
+        so += up ? 0u : 1u;
+      }
+    }
+  }
+}
+
+// incl_bwd01: layers 0 and 1 in one launch, one workgroup per tile of layer 1.  Each thread
+// runs the blend adjoint of its layer-1 texel and then of the four layer-0 texels it covers,
+// whose items taken from it are added to its totals straight from registers (through a
+// per-thread LDS column), so layer 0 passes nothing up through memory.  Same totals and
+// summation order as two launches of incl_bwd.
+template <int D>
+__global__ __launch_bounds__(256) void k_incl_bwd01(
+    const Params P, const uint64_t* __restrict__ fkey, const float* __restrict__ fgam,
+    const uint32_t* __restrict__ fcnt, const float* __restrict__ desc,
+    const float* __restrict__ gpyr, float* __restrict__ itot, float* __restrict__ iup_out,
+    const Extras X) {
+  constexpr int S = D + 1;
+  __shared__ float s_dg[KEEP][TP];  // a child's items taken from this texel, in order
+  __shared__ float s_tg[KEEP][TP];
+  const int v = blockIdx.y;
+  const ViewP& c = P.view[v];
+  const uint32_t local = blockIdx.x;
+  if (local >= c.lbin[2] - c.lbin[1]) return;
+  const uint32_t b = c.lbin[1] + local;
+  const int t = threadIdx.x;
+  const int lth = 8 - P.ltw;
+  const int W1 = layer_dim(c.W, 1), H1 = layer_dim(c.H, 1);
+  const int W0 = layer_dim(c.W, 0), H0 = layer_dim(c.H, 0);
+  const int tiles_x = (W1 + (1 << P.ltw) - 1) >> P.ltw;
+  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  const int i = (tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+  const int j = (ty << lth) + (t >> P.ltw);
+  if (!(i < W1 && j < H1)) return;  // (no barrier follows)
+  const size_t tb = size_t(b) * KEEP;
+  const uint32_t fc = fcnt[size_t(b) * TP + t];
+  const uint32_t mask = fc >> 16;
+  float tot[KEEP][S];
+  uint32_t k;
+  {
+    float G[D], dg[KEEP], tg[KEEP];
+    k = blended_adjoint<D>(fkey, fgam, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, desc,
+                           gpyr, X, G, dg, tg);
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) {
+      tot[m][0] = dg[m];
+#pragma unroll
+      for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
+    }
+  }
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const int ci = 2 * i + (q & 1), cj = 2 * j + (q >> 1);
+    if (!(ci < W0 && cj < H0)) continue;
+    uint32_t cb;
+    int ct;
+    texel_bin(P, v, 0, ci, cj, cb, ct);
+    const uint32_t cfc = fcnt[size_t(cb) * TP + ct];
+    const uint32_t cmask = cfc >> 16;
+    float G[D], dg[KEEP], tg[KEEP];
+    const uint32_t ck = blended_adjoint<D>(fkey, fgam, cb, ct, cfc,
+                                           size_t(c.lout[0]) + size_t(cj) * W0 + ci, desc, gpyr,
+                                           X, G, dg, tg);
+    const size_t ctb = size_t(cb) * KEEP;
+    uint32_t so = 0, sp = 0;
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) {
+      if (uint32_t(m) < ck) {
+        if ((cmask >> m) & 1u) {
+          s_dg[sp][t] = dg[m];
+          s_tg[sp][t] = tg[m];
+          ++sp;
+        } else {
+          float* dst = itot + ((ctb + so) * S) * TP + ct;
+          dst[0] = dg[m];
+#pragma unroll
+          for (int d = 0; d < D; ++d) dst[size_t(1 + d) * TP] = tg[m] * G[d];
+          ++so;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m)
+      if (uint32_t(m) < sp) {
+        tot[m][0] += s_dg[m][t];
+        const float w = s_tg[m][t];
+#pragma unroll
+        for (int d = 0; d < D; ++d) tot[m][1 + d] += w * G[d];
+      }
+  }
   uint32_t so = 0, sp = 0;
 #pragma unroll
   for (int m = 0; m < KEEP; ++m) {
     if (uint32_t(m) < k) {
-      float tot[S];
-      tot[0] = dg[m];
-#pragma unroll
-      for (int d = 0; d < D; ++d) tot[1 + d] = tg[m] * G[d];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (uint32_t(m) < cup[q]) {
-#pragma unroll
-          for (int r = 0; r < S; ++r) tot[r] += iup[cbase[q] + (size_t(m) * S + r) * TP];
-        }
       const bool up = (mask >> m) & 1u;
-      float* dst = up ? iup + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
+      float* dst = up ? iup_out + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
 #pragma unroll
-      for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[r];
+      for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
       sp += up ? 1u : 0u;
       so += up ? 0u : 1u;
     }
@@ -1896,9 +2046,14 @@ __global__ __launch_bounds__(256) void k_bwd_points(
       float gt[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) gt[d] = 0.0f;
-      // both layer entries' footprints and entry positions first, then their rows
-      uint32_t tm[2][4], epo[2][4];
+      // both layer entries' footprints and the point's eight entry positions (one 32-byte
+      // record), then all eight rows at once: a slot without an entry reads row 0 and is
+      // dropped, so no load waits on another
+      uint32_t tm[2][4];
       const uint32_t last = uint32_t(8 * P.n * P.V) - 1u;  // row capacity (guards memory only)
+      const uint4* ep4 = reinterpret_cast<const uint4*>(epos + (size_t(v) * size_t(P.n) + size_t(p)) * NSLOT);
+      const uint4 ea = ep4[0], eb = ep4[1];
+      const uint32_t er[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
 #pragma unroll
       for (int sel = 0; sel < 2; ++sel) {
         const int L = g.L0 + sel;
@@ -1906,28 +2061,35 @@ __global__ __launch_bounds__(256) void k_bwd_points(
         const bool ok = sel < g.nl && footprint(g.x, g.y, L, layer_dim(c.W, L), layer_dim(c.H, L), ft);
         if (ok) touches(ft, P.ltw, tm[sel]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 4; ++q)
           if (!ok) tm[sel][q] = 0;
-          epo[sel][q] = tm[sel][q] ? min(epos[(size_t(v) * NSLOT + sel * 4 + q) * size_t(P.n) + size_t(p)], last) : 0u;
-        }
       }
+      float4 rv[2][4][1 + D / 4];
+#pragma unroll
+      for (int sel = 0; sel < 2; ++sel)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t e = tm[sel][q] ? min(er[sel * 4 + q], last) : 0u;
+          const float4* r4 = reinterpret_cast<const float4*>(rows + size_t(e) * RW);
+#pragma unroll
+          for (int qq = 0; qq < 1 + D / 4; ++qq) rv[sel][q][qq] = r4[qq];
+        }
 #pragma unroll
       for (int sel = 0; sel < 2; ++sel) {
-        if (sel >= g.nl) break;
         const int L = g.L0 + sel;
         float sA = 0.f, sBx = 0.f, sBy = 0.f;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (!tm[sel][q]) continue;
-          const float4* r4 = reinterpret_cast<const float4*>(rows + size_t(epo[sel][q]) * RW);
-          const float4 h = r4[0];
+          const float4 h = rv[sel][q][0];
           sA += h.x; sBx += h.y; sBy += h.z;
 #pragma unroll
           for (int qq = 0; qq < D / 4; ++qq) {
-            const float4 tv = r4[1 + qq];
+            const float4 tv = rv[sel][q][1 + qq];
             gt[4 * qq] += tv.x; gt[4 * qq + 1] += tv.y; gt[4 * qq + 2] += tv.z; gt[4 * qq + 3] += tv.w;
           }
         }
+        if (sel >= g.nl) break;
         const float io = g.io[sel];
         const float sc = pow2i(-L);
         gal += sA * io;
@@ -2356,9 +2518,16 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     float* iup = reinterpret_cast<float*>(ws + lay.w_iup);
     {
       StageTimer tm(ST_INCL_BWD, st);
-      for (int L = 0; L < P.nl; ++L) {
+      // the two finest layers run as one launch (layer 0 passes nothing up through memory)
+      const bool fuse = P.nl > 1;
+      if (fuse) {
+        hipLaunchKernelGGL(k_incl_bwd01<D>, dim3(layer_tiles_max(P, 1), uint32_t(P.V)), dim3(256),
+                           0, st, P, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, X);
+        TRIPS_HIP(hipGetLastError());
+      }
+      for (int L = fuse ? 2 : 0; L < P.nl; ++L) {
         hipLaunchKernelGGL(k_incl_bwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256), 0,
-                           st, P, L, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, X);
+                           st, P, L, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, iup, X);
         TRIPS_HIP(hipGetLastError());
       }
     }
