@@ -323,11 +323,17 @@ __device__ __forceinline__ void for_each_entry(const Params& P, const ViewP& c, 
     touches(ft, P.ltw, tm);
     int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
     int txb = ft.i0 >> P.ltw, tyb = ft.j0 >> (8 - P.ltw);
+    // first bin of layer L: L differs between lanes, so it is selected from the view's
+    // (wave-uniform, scalar) table rather than indexed, which would be a vector memory load
+    // that waits for the caller's earlier stores
+    uint32_t lbase = c.lbin[0];
+#pragma unroll
+    for (int k = 1; k < MAXL; ++k) lbase = L == k ? c.lbin[k] : lbase;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (!tm[t]) continue;
       int tx = txb + (t & 1), ty = tyb + (t >> 1);
-      uint32_t bin = c.lbin[L] + uint32_t(ty * tiles_x + tx);
+      uint32_t bin = lbase + uint32_t(ty * tiles_x + tx);
       f(bin, uint32_t(sel * 4 + t), sel, ft, g);
     }
   }
@@ -1661,12 +1667,15 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
     fcnt[size_t(b) * TP + t] = ko;
     return;
   }
-  // all 16 slots are staged (slots past the list hold stale values and are never read), so
-  // the loads do not wait on one another
+  // slots are staged whatever the list length (stale values past it are never read), so
+  // their loads do not wait on one another: all 16 in the coarser layers, the first four in
+  // the two finest (longer own lists are rare there and load the rest)
 #pragma unroll
   for (int m = 0; m < KEEP; ++m) {
-    s_ok[m][t] = kkey[(tb + m) * TP + t];
-    s_og[m][t] = kgam[(tb + m) * TP + t];
+    if (m < 4 || L >= 2 || uint32_t(m) < ko) {
+      s_ok[m][t] = kkey[(tb + m) * TP + t];
+      s_og[m][t] = kgam[(tb + m) * TP + t];
+    }
   }
   {  // the covering texels: (tw/2) x (th/2) texels of one tile of layer L + 1
     const int hw = 1 << (P.ltw - 1);
