@@ -626,13 +626,19 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
   const int64_t p0 = int64_t(blk) * P.pb;
   const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
   uint32_t vis = 0;
-  // one point ahead, as in the count pass
-  int64_t pn = p0 + threadIdx.x;
-  int64_t pc = min(pn, p1 - 1);
+  // two points ahead: a load issued after this point's entry stores would wait for them
+  // (one in-order counter), so the point used next was requested a point earlier
+  const int64_t pn = p0 + threadIdx.x;
+  const int64_t st = blockDim.x;
   float x = 0.f, y = 0.f, z = 0.f, sw = 0.f, al = 0.f;
-  if (pn < p1) { x = X[pc]; y = Y[pc]; z = Z[pc]; sw = SW[pc]; al = A[pc]; }
-  for (int64_t p = pn; p < p1; p += blockDim.x) {
-    pc = min(p + int64_t(blockDim.x), p1 - 1);
+  float x1 = 0.f, y1 = 0.f, z1 = 0.f, sw1 = 0.f, al1 = 0.f;
+  if (pn < p1) {
+    const int64_t q0 = pn, q1 = min(pn + st, p1 - 1);
+    x = X[q0]; y = Y[q0]; z = Z[q0]; sw = SW[q0]; al = A[q0];
+    x1 = X[q1]; y1 = Y[q1]; z1 = Z[q1]; sw1 = SW[q1]; al1 = A[q1];
+  }
+  for (int64_t p = pn; p < p1; p += st) {
+    const int64_t pc = min(p + 2 * st, p1 - 1);
     const float xn = X[pc], yn = Y[pc], zn = Z[pc], swn = SW[pc], aln = A[pc];
     const float alpha = al;
     bool any = false;
@@ -662,7 +668,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
       ep4[1] = make_uint4(er[4], er[5], er[6], er[7]);
     }
     vis += any ? 1u : 0u;
-    x = xn; y = yn; z = zn; sw = swn; al = aln;
+    x = x1; y = y1; z = z1; sw = sw1; al = al1;
+    x1 = xn; y1 = yn; z1 = zn; sw1 = swn; al1 = aln;
   }
   // number of (point, view) pairs with at least one entry, for reports
   atomicAdd(&s_vis, vis);
