@@ -1731,6 +1731,8 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
   for (int d = 0; d < D; ++d) C[d] = 0.0f;
   float T = 1.0f;
   constexpr int GB = D > 4 ? 4 : 8;
+  // without points every list is empty and there is no point 0 to read (uniform branch)
+  if (P.n > 0) {
 #pragma unroll
   for (int m0 = 0; m0 < KEEP; m0 += GB) {
     // a batch of descriptor gathers, all issued before use (an empty slot reads point 0)
@@ -1759,6 +1761,7 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
       }
     }
   }
+  }
 #pragma unroll
   for (int m = 0; m < KEEP; ++m)
     if (uint32_t(m) < k) {
@@ -1771,11 +1774,12 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
 
 // Blend adjoint of the blended list of one texel (tile b, slot t, pyramid texel tex; fc its
 // count word): G, and per item m < k dg[m] = dL/dgamma_m and tg[m] = T_m gamma_m (zero past
-// k); writes the background gradient.  Returns k.
+// k); writes the background gradient.  Returns k.  has_points: the cloud is not empty (an
+// empty slot then reads point 0's descriptor, which exists).
 template <int D>
 __device__ __forceinline__ uint32_t blended_adjoint(const uint64_t* __restrict__ fkey,
                                                     const float* __restrict__ fgam, uint32_t b,
-                                                    int t, uint32_t fc, size_t tex,
+                                                    int t, uint32_t fc, size_t tex, bool has_points,
                                                     const float* __restrict__ desc,
                                                     const float* __restrict__ gpyr, const Extras& X,
                                                     float (&G)[D], float (&dg)[KEEP],
@@ -1809,16 +1813,20 @@ __device__ __forceinline__ uint32_t blended_adjoint(const uint64_t* __restrict__
   }
   constexpr int GB = D > 4 ? 4 : 8;
 #pragma unroll
-  for (int m0 = 0; m0 < KEEP; m0 += GB) {
-    float4 tv[GB][D / 4];  // empty slots read point 0 and are dropped
+  for (int m = 0; m < KEEP; ++m) gm[m] = 0.0f;
+  if (has_points) {  // uniform; without points k is 0
 #pragma unroll
-    for (int q = 0; q < GB; ++q) {
-      const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx[m0 + q]) * D);
+    for (int m0 = 0; m0 < KEEP; m0 += GB) {
+      float4 tv[GB][D / 4];  // empty slots read point 0 and are dropped
 #pragma unroll
-      for (int r = 0; r < D / 4; ++r) tv[q][r] = tp[r];
+      for (int q = 0; q < GB; ++q) {
+        const float4* tp = reinterpret_cast<const float4*>(desc + size_t(idx[m0 + q]) * D);
+#pragma unroll
+        for (int r = 0; r < D / 4; ++r) tv[q][r] = tp[r];
+      }
+#pragma unroll
+      for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
     }
-#pragma unroll
-    for (int q = 0; q < GB; ++q) gm[m0 + q] = dot_g<D>(G, tv[q]);
   }
   if (X.galpha) {
     const float ga = X.galpha[tex];
@@ -1872,7 +1880,8 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   const uint32_t mask = fc >> 16;
   const size_t tex = size_t(c.lout[L]) + size_t(j) * WL + i;
   float G[D], dg[KEEP], tg[KEEP];
-  const uint32_t k = blended_adjoint<D>(fkey, fgam, b, t, fc, tex, desc, gpyr, X, G, dg, tg);
+  const uint32_t k = blended_adjoint<D>(fkey, fgam, b, t, fc, tex, P.n > 0, desc, gpyr, X, G, dg,
+                                        tg);
   // the finer texels this texel covers, and how many of its items each of them took
   size_t cbase[4];
   uint32_t cup[4];
@@ -1965,8 +1974,8 @@ __global__ __launch_bounds__(256) void k_incl_bwd01(
   uint32_t k;
   {
     float G[D], dg[KEEP], tg[KEEP];
-    k = blended_adjoint<D>(fkey, fgam, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, desc,
-                           gpyr, X, G, dg, tg);
+    k = blended_adjoint<D>(fkey, fgam, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i,
+                           P.n > 0, desc, gpyr, X, G, dg, tg);
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) {
       tot[m][0] = dg[m];
@@ -1985,8 +1994,8 @@ __global__ __launch_bounds__(256) void k_incl_bwd01(
     const uint32_t cmask = cfc >> 16;
     float G[D], dg[KEEP], tg[KEEP];
     const uint32_t ck = blended_adjoint<D>(fkey, fgam, cb, ct, cfc,
-                                           size_t(c.lout[0]) + size_t(cj) * W0 + ci, desc, gpyr,
-                                           X, G, dg, tg);
+                                           size_t(c.lout[0]) + size_t(cj) * W0 + ci, P.n > 0, desc,
+                                           gpyr, X, G, dg, tg);
     const size_t ctb = size_t(cb) * KEEP;
     uint32_t so = 0, sp = 0;
 #pragma unroll

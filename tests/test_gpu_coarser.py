@@ -200,3 +200,38 @@ def test_full_size_sampled_texels(gpu):
     got = _gpu(sc, gpu, bg, G, Ga)
     got["gcam"] = got["gcam"][0]
     _check_view(got, sc, cam, bg, G, Ga, mask=mask, where="full size ")
+
+
+def test_no_points_and_all_culled(gpu):
+    """An empty cloud and a cloud entirely behind the camera: every texel shows the
+    background, the coverage is 0 and the background gradient is G."""
+    import torch
+    import paper_2401_06003_amd as tp
+    sc = scenes.random_small(514, n=50, W=40, H=30, nlayers=4)
+    cam = sc["cams"][0]
+    P = oracle.num_pixels(cam["W"], cam["H"], sc["nlayers"])
+    bg, G, Ga = _inputs(P, sc["D"], 130)
+    behind = dict(sc["points"], z=(-sc["points"]["z"]).astype(np.float32))
+    for pts in (behind, {k: v[:0] for k, v in sc["points"].items()}):
+        s2 = dict(sc, points=pts)
+        got = _gpu(s2, gpu, bg, G, Ga)
+        assert np.array_equal(got["pyr"], bg.astype(np.float64))
+        assert not got["coverage"].any() and not got["counts"].any() and (got["ids"] == -1).all()
+        assert np.array_equal(got["gbg"], G.astype(np.float64))
+        assert not got["gcam"].any()
+        for k in PARAMS:
+            assert not got[k].any(), k
+
+
+def test_two_layers_and_deep_pyramid(gpu):
+    """Two layers (only the fused finest pass) and twelve (layers down to 1x1 texel, huge
+    splats), with a tile width whose covering block spans one tile row."""
+    import paper_2401_06003_amd as tp
+    for nl, tw in ((2, 16), (12, 64)):
+        sc = scenes.random_small(515, n=400, W=70, H=50, nlayers=nl, s_lo=0.2, s_hi=3000.0)
+        cam = sc["cams"][0]
+        P = oracle.num_pixels(cam["W"], cam["H"], nl)
+        bg, G, Ga = _inputs(P, sc["D"], 140 + nl)
+        got = _gpu(sc, gpu, bg, G, Ga, tp.make_tuning(tw, 0, 0))
+        got["gcam"] = got["gcam"][0]
+        _check_view(got, sc, cam, bg, G, Ga, where="layers %d " % nl)
