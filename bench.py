@@ -42,10 +42,11 @@ def kernel_bytes(stage, w):
 
     w: workload counts.  N points, D channels, E tile entries (E_f of them in fine tiles,
     the tiles of at most 256 entries, which are rendered and differentiated whole with one
-    descriptor read per entry), K kept fragments (K_f in fine tiles), NB tiles (NB_f fine),
+    descriptor read per entry), K kept fragments (K_f in fine tiles), Nv points with entries
+    (each has a 32-byte record of its entry positions), NB tiles (NB_f fine),
     I_c work items of the other tiles, P texels inside the layers, Ppad = 256 NB, nblk point
     blocks.  Texels of a set of tiles inside the layers are counted pro rata."""
-    N, D, E, Ef, K, Kf = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"]
+    N, D, E, Ef, K, Kf, Nv = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"], w["Nv"]
     NB, NBf, Ic, P, nblk = w["NB"], w["NB_f"], w["I_c"], w["P"], w["nblk"]
     Ppad = 256 * NB
     Ec, Kc, NBc = E - Ef, K - Kf, NB - NBf
@@ -54,13 +55,13 @@ def kernel_bytes(stage, w):
     table = {
         "count": 16 * N + 4 * nblk * NB,
         "colscan": 8 * nblk * NB + 4 * NB,
-        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 28 * E,
+        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 24 * E + 32 * Nv,
         "fwd_items": 24 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
         "fwd_fine": (28 + 4 * D) * Ef + 12 * Kf + 4 * 256 * NBf + 4 * D * Pf,
         "bwd_pixels": 4 * 256 * NBc + (12 + 4 * D + 8) * Kc + 4 * D * Pc,
         "bwd_items": (24 + row) * Ec + 16 * Kc + Ic * 256 * (4 + 4 * D),
         "bwd_fine": (24 + 4 * D + row) * Ef + 4 * 256 * NBf + 4 * D * Pf,
-        "bwd_points": 20 * N + (4 + row) * E + 4 * (5 + D) * N,
+        "bwd_points": 20 * N + 32 * Nv + row * E + 4 * (5 + D) * N,
     }
     return table.get(stage)
 
@@ -271,7 +272,7 @@ def main():
     w = {"N": N, "D": D, "E": E, "E_f": int(tile_e[fine].sum()), "K": K,
          "K_f": int(tile_k[fine].sum()), "NB": NB, "NB_f": int(fine.sum()),
          "I_c": int(((tile_e[~fine].astype(np.int64) + item_e - 1) // item_e).sum()), "P": P,
-         "nblk": nblk}
+         "nblk": nblk, "Nv": Nv}
 
     # the step captured once in a HIP graph (forward then backward), replayed per step
     plan = tp.Plan(r, *pargs, pyr, G, grads)
