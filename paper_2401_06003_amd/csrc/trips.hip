@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -307,7 +308,10 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t value) {
 }
 
 // Emits every tile entry of one point for view c; calls f(bin, slot, sel, foot, geo).
-template <class F>
+// SELECT: take the layer's first tile from a select over the view's (wave-uniform, scalar)
+// table instead of indexing it with the per-lane layer, which is a vector memory load; a
+// caller that stores between entries needs that (the load would wait for its stores).
+template <bool SELECT, class F>
 __device__ __forceinline__ void for_each_entry(const Params& P, const ViewP& c, float X, float Y,
                                                float Z, float sw, F&& f) {
   Geo g;
@@ -323,12 +327,14 @@ __device__ __forceinline__ void for_each_entry(const Params& P, const ViewP& c, 
     touches(ft, P.ltw, tm);
     int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
     int txb = ft.i0 >> P.ltw, tyb = ft.j0 >> (8 - P.ltw);
-    // first bin of layer L: L differs between lanes, so it is selected from the view's
-    // (wave-uniform, scalar) table rather than indexed, which would be a vector memory load
-    // that waits for the caller's earlier stores
-    uint32_t lbase = c.lbin[0];
+    uint32_t lbase;
+    if (SELECT) {
+      lbase = c.lbin[0];
 #pragma unroll
-    for (int k = 1; k < MAXL; ++k) lbase = L == k ? c.lbin[k] : lbase;
+      for (int k = 1; k < MAXL; ++k) lbase = L == k ? c.lbin[k] : lbase;
+    } else {
+      lbase = c.lbin[L];
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (!tm[t]) continue;
@@ -366,7 +372,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const flo
   for (; p < p1; p += blockDim.x) {
     pc = min(p + int64_t(blockDim.x), p1 - 1);
     const float xn = X[pc], yn = Y[pc], zn = Z[pc], swn = SW[pc];
-    for_each_entry(P, c, x, y, z, sw,
+    for_each_entry<false>(P, c, x, y, z, sw,
                    [&](uint32_t bin, uint32_t, int, const Foot&, const Geo&) {
                      add16(hist, bin - c.bin_base);
                    });
@@ -645,7 +651,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
     uint32_t er[NSLOT];  // the point's entry positions, written as one 32-byte record
 #pragma unroll
     for (int k = 0; k < NSLOT; ++k) er[k] = 0u;
-    for_each_entry(P, c, x, y, z, sw,
+    for_each_entry<true>(P, c, x, y, z, sw,
                    [&](uint32_t bin, uint32_t slot, int sel, const Foot& ft, const Geo& g) {
                      any = true;
                      const uint32_t lb = bin - c.bin_base;
@@ -2414,6 +2420,39 @@ trips_status check_points(const trips_points* pts, const Layout& lay) {
   return TRIPS_OK;
 }
 
+// A second stream per device for the fine-tile kernels, which touch other tiles than the
+// work-item kernels and run beside them (a fork and a join on the caller's stream; in a
+// captured plan these become two branches of the graph).  Created on first use with the
+// default priority and kept until the process ends; g_side_launch serialises the calls that
+// use it, so the fork and join events of one call are never interleaved with another's.
+struct SideStream {
+  hipStream_t s;
+  hipEvent_t fork, join;
+};
+std::mutex g_side_make, g_side_launch;
+constexpr int kMaxDevices = 64;
+SideStream g_side[kMaxDevices];
+
+trips_status side_stream(SideStream*& out) {
+  int dev = 0;
+  TRIPS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return TRIPS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_side_make);
+  SideStream& sd = g_side[dev];
+  if (!sd.s) {
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    TRIPS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    TRIPS_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    TRIPS_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    sd.fork = a;
+    sd.join = b;
+    sd.s = s;
+  }
+  out = &sd;
+  return TRIPS_OK;
+}
+
 // Largest tile count of layer L over the views (grid width of the per-layer passes).
 uint32_t layer_tiles_max(const Params& P, int L) {
   uint32_t m = 0;
@@ -2483,24 +2522,41 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
                          pts.opacity, H, bin_start, ent, epos, info);
   }
   TRIPS_HIP(hipGetLastError());
-  {  // one workgroup per work item; workgroups beyond the item count exit at once
-    StageTimer tm(ST_FWD_ITEMS, st);
-    hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info, work,
-                       ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam, X.bg, X.alpha);
-  }
-  TRIPS_HIP(hipGetLastError());
-  {  // one workgroup per fine tile; workgroups beyond their count exit at once
-    StageTimer tm(ST_FWD_FINE, st);
-    hipLaunchKernelGGL(k_fwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent,
-                       pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
-  }
-  TRIPS_HIP(hipGetLastError());
   {
-    StageTimer tm(ST_FWD_MERGE, st);
-    hipLaunchKernelGGL(k_fwd_merge<D>, dim3(1024), dim3(256), 0, st, P, item_start, multi_bins,
-                       info, pcnt, pkey, pgam, pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
+    // the fine tiles on the side stream, beside the work items and their merge
+    SideStream* sd = nullptr;
+    trips_status ss = side_stream(sd);
+    if (ss != TRIPS_OK) return ss;
+    std::lock_guard<std::mutex> lk(g_side_launch);
+    TRIPS_HIP(hipEventRecord(sd->fork, st));
+    TRIPS_HIP(hipStreamWaitEvent(sd->s, sd->fork, 0));
+    {  // one workgroup per fine tile; workgroups beyond their count exit at once
+      StageTimer tm(ST_FWD_FINE, sd->s);
+      hipLaunchKernelGGL(k_fwd_fine<D>, dim3(P.NB), dim3(256), 0, sd->s, P, info, fine_work, ent,
+                         pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
+    }
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipEventRecord(sd->join, sd->s);
+    {  // one workgroup per work item; workgroups beyond the item count exit at once
+      StageTimer tm(ST_FWD_ITEMS, st);
+      hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info,
+                         work, ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam, X.bg,
+                         X.alpha);
+    }
+    hipError_t e3 = hipGetLastError();
+    {
+      StageTimer tm(ST_FWD_MERGE, st);
+      hipLaunchKernelGGL(k_fwd_merge<D>, dim3(1024), dim3(256), 0, st, P, item_start, multi_bins,
+                         info, pcnt, pkey, pgam, pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
+    }
+    hipError_t e4 = hipGetLastError();
+    // the join is enqueued whatever failed, so a captured graph has no dangling branch
+    TRIPS_HIP(hipStreamWaitEvent(st, sd->join, 0));
+    TRIPS_HIP(e1);
+    TRIPS_HIP(e2);
+    TRIPS_HIP(e3);
+    TRIPS_HIP(e4);
   }
-  TRIPS_HIP(hipGetLastError());
   if (P.coarser) {  // coarsest layer first: each layer merges the blended lists above it
     StageTimer tm(ST_INCL_FWD, st);
     uint64_t* fkey = reinterpret_cast<uint64_t*>(sv + lay.s_fkey);
@@ -2564,25 +2620,38 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     }
     TRIPS_HIP(hipGetLastError());
   } else {
+    // the fine tiles on the side stream, beside the blend adjoints and rows of the items
+    SideStream* sd = nullptr;
+    trips_status ss = side_stream(sd);
+    if (ss != TRIPS_OK) return ss;
+    std::lock_guard<std::mutex> lk(g_side_launch);
+    TRIPS_HIP(hipEventRecord(sd->fork, st));
+    TRIPS_HIP(hipStreamWaitEvent(sd->s, sd->fork, 0));
+    {
+      StageTimer tm(ST_BWD_FINE, sd->s);
+      hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, sd->s, P, info, fine_work, ent,
+                         npix, pts.desc, gpyr, rows, X);
+    }
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipEventRecord(sd->join, sd->s);
     {
       StageTimer tm(ST_BWD_PIXELS, st);
       hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
                          kkey, kgam, pts.desc, gpyr, bst, X);
     }
-    TRIPS_HIP(hipGetLastError());
+    hipError_t e3 = hipGetLastError();
     {
       StageTimer tm(ST_BWD_ITEMS, st);
       hipLaunchKernelGGL((k_bwd_items<D, false>), dim3(uint32_t(lay.icap) * BWD_SPLIT), dim3(256),
                          0, st, P, info, work, ent, npix, kkey, bst, gpyr, rows, BWD_SPLIT,
                          nullptr, nullptr);
     }
-    TRIPS_HIP(hipGetLastError());
-    {
-      StageTimer tm(ST_BWD_FINE, st);
-      hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, st, P, info, fine_work, ent, npix,
-                         pts.desc, gpyr, rows, X);
-    }
-    TRIPS_HIP(hipGetLastError());
+    hipError_t e4 = hipGetLastError();
+    TRIPS_HIP(hipStreamWaitEvent(st, sd->join, 0));
+    TRIPS_HIP(e1);
+    TRIPS_HIP(e2);
+    TRIPS_HIP(e3);
+    TRIPS_HIP(e4);
   }
   if (P.n > 0) {
     StageTimer tm(ST_BWD_POINTS, st);
@@ -2891,6 +2960,11 @@ trips_status trips_plan_create(const trips_config* cfg, const trips_points* pts,
   pl->pts = *pts;
   pl->pyr = pyr; pl->saved = saved; pl->ws = ws; pl->gpyr = gpyr;
   pl->gx = gx; pl->gy = gy; pl->gz = gz; pl->gsw = gsw; pl->ga = ga; pl->gd = gd;
+  {  // the side stream is created before any capture begins
+    SideStream* sd = nullptr;
+    trips_status ss = side_stream(sd);
+    if (ss != TRIPS_OK) { trips_plan_destroy(pl); return ss; }
+  }
   for (int which = 1; which <= 3; ++which) {
     pl->exec[which - 1] = nullptr;
     if ((which & 2) && !bwd) continue;
