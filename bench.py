@@ -316,8 +316,8 @@ def main():
     ms_graph = timed(step_graph)
     log("timed %d eager steps" % args.steps)
     ms_eager = timed(step)
-    # the same launch sequence either way; the faster mode is the headline (on this ROCm the
-    # graph does not run the fine-tile branch beside the work items, the two streams do)
+    # the same launch sequence either way (the fine-tile kernels on a second stream beside the
+    # work items, a graph branch when captured); the faster mode is the headline
     ms, mode = (ms_graph, "graph") if ms_graph <= ms_eager else (ms_eager, "eager")
     # per-kernel durations: the eager steps again, every launch bracketed by HIP events
     log("timed %d eager steps with per-kernel events" % args.steps)

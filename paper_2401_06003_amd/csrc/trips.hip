@@ -2529,7 +2529,15 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     if (ss != TRIPS_OK) return ss;
     std::lock_guard<std::mutex> lk(g_side_launch);
     TRIPS_HIP(hipEventRecord(sd->fork, st));
-    TRIPS_HIP(hipStreamWaitEvent(sd->s, sd->fork, 0));
+    {  // one workgroup per work item (the longer path, enqueued first); workgroups beyond the
+       // item count exit at once
+      StageTimer tm(ST_FWD_ITEMS, st);
+      hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info,
+                         work, ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam, X.bg,
+                         X.alpha);
+    }
+    hipError_t e3 = hipGetLastError();
+    hipError_t e0 = hipStreamWaitEvent(sd->s, sd->fork, 0);
     {  // one workgroup per fine tile; workgroups beyond their count exit at once
       StageTimer tm(ST_FWD_FINE, sd->s);
       hipLaunchKernelGGL(k_fwd_fine<D>, dim3(P.NB), dim3(256), 0, sd->s, P, info, fine_work, ent,
@@ -2537,13 +2545,6 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     }
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipEventRecord(sd->join, sd->s);
-    {  // one workgroup per work item; workgroups beyond the item count exit at once
-      StageTimer tm(ST_FWD_ITEMS, st);
-      hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info,
-                         work, ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam, X.bg,
-                         X.alpha);
-    }
-    hipError_t e3 = hipGetLastError();
     {
       StageTimer tm(ST_FWD_MERGE, st);
       hipLaunchKernelGGL(k_fwd_merge<D>, dim3(1024), dim3(256), 0, st, P, item_start, multi_bins,
@@ -2552,6 +2553,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     hipError_t e4 = hipGetLastError();
     // the join is enqueued whatever failed, so a captured graph has no dangling branch
     TRIPS_HIP(hipStreamWaitEvent(st, sd->join, 0));
+    TRIPS_HIP(e0);
     TRIPS_HIP(e1);
     TRIPS_HIP(e2);
     TRIPS_HIP(e3);
@@ -2626,7 +2628,13 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     if (ss != TRIPS_OK) return ss;
     std::lock_guard<std::mutex> lk(g_side_launch);
     TRIPS_HIP(hipEventRecord(sd->fork, st));
-    TRIPS_HIP(hipStreamWaitEvent(sd->s, sd->fork, 0));
+    {  // the longer path first
+      StageTimer tm(ST_BWD_PIXELS, st);
+      hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
+                         kkey, kgam, pts.desc, gpyr, bst, X);
+    }
+    hipError_t e3 = hipGetLastError();
+    hipError_t e0 = hipStreamWaitEvent(sd->s, sd->fork, 0);
     {
       StageTimer tm(ST_BWD_FINE, sd->s);
       hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, sd->s, P, info, fine_work, ent,
@@ -2635,12 +2643,6 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipEventRecord(sd->join, sd->s);
     {
-      StageTimer tm(ST_BWD_PIXELS, st);
-      hipLaunchKernelGGL(k_bwd_pixels<D>, dim3(P.NB), dim3(256), 0, st, P, info, coarse_bins, npix,
-                         kkey, kgam, pts.desc, gpyr, bst, X);
-    }
-    hipError_t e3 = hipGetLastError();
-    {
       StageTimer tm(ST_BWD_ITEMS, st);
       hipLaunchKernelGGL((k_bwd_items<D, false>), dim3(uint32_t(lay.icap) * BWD_SPLIT), dim3(256),
                          0, st, P, info, work, ent, npix, kkey, bst, gpyr, rows, BWD_SPLIT,
@@ -2648,6 +2650,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     }
     hipError_t e4 = hipGetLastError();
     TRIPS_HIP(hipStreamWaitEvent(st, sd->join, 0));
+    TRIPS_HIP(e0);
     TRIPS_HIP(e1);
     TRIPS_HIP(e2);
     TRIPS_HIP(e3);
