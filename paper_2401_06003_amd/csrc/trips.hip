@@ -1156,24 +1156,37 @@ __global__ __launch_bounds__(256) void k_fwd_merge(
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
     uint32_t n = 0;
-    for (uint32_t it = i0 + slice; it < i1; it += 4) {
-      n += pcnt[size_t(it) * TP + t];
-      // a partial list holds min(count, 16) ascending keys, then KEY_NONE
+    // a partial list holds min(count, 16) ascending keys, then KEY_NONE; the next item's list
+    // is loaded while the current one is merged
+    auto load = [&](uint32_t it, uint4 (&k4)[KEEP / 2], float4 (&g4)[KEEP / 4], uint32_t& c) {
       const uint4* pk = reinterpret_cast<const uint4*>(pkey + (size_t(it) * TP + t) * KEEP);
       const float4* pg = reinterpret_cast<const float4*>(pgam + (size_t(it) * TP + t) * KEEP);
+#pragma unroll
+      for (int m = 0; m < KEEP / 2; ++m) k4[m] = pk[m];
+#pragma unroll
+      for (int m = 0; m < KEEP / 4; ++m) g4[m] = pg[m];
+      c = pcnt[size_t(it) * TP + t];
+    };
+    uint4 k4[KEEP / 2];
+    float4 g4[KEEP / 4];
+    uint32_t c = 0;
+    uint32_t it = i0 + slice;
+    if (it < i1) load(it, k4, g4, c);
+    while (it < i1) {
       uint64_t ok[KEEP];
       float og[KEEP];
 #pragma unroll
       for (int m = 0; m < KEEP; m += 2) {
-        const uint4 v = pk[m / 2];
-        ok[m] = (uint64_t(v.y) << 32) | v.x;
-        ok[m + 1] = (uint64_t(v.w) << 32) | v.z;
+        ok[m] = (uint64_t(k4[m / 2].y) << 32) | k4[m / 2].x;
+        ok[m + 1] = (uint64_t(k4[m / 2].w) << 32) | k4[m / 2].z;
       }
 #pragma unroll
       for (int m = 0; m < KEEP; m += 4) {
-        const float4 v = pg[m / 4];
-        og[m] = v.x; og[m + 1] = v.y; og[m + 2] = v.z; og[m + 3] = v.w;
+        og[m] = g4[m / 4].x; og[m + 1] = g4[m / 4].y; og[m + 2] = g4[m / 4].z; og[m + 3] = g4[m / 4].w;
       }
+      n += c;
+      it += 4;
+      if (it < i1) load(it, k4, g4, c);
       merge16(kk, kg, ok, og);
     }
     if (slice > 0) {
