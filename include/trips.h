@@ -16,6 +16,10 @@
  *    that returns an error launched nothing.  HIP launch failures return
  *    TRIPS_ERR_HIP and the HIP error code is kept for trips_last_hip_error().
  *  - All work is enqueued on `stream` in order; results are ready when the stream is.
+ *    Part of a forward or backward call (the kernels of the tiles with few entries) runs on
+ *    a second stream of the device that the library creates once, with the default
+ *    priority, forked from `stream` and joined back into it within the call; captured into
+ *    a graph, the two become branches of it.
  *  - Up to TRIPS_MAX_VIEWS views of arbitrary, different resolutions are rendered by
  *    one call ("batched views"); every point is read once per call and projected
  *    into every view.  Gradients are summed over the views of a call.
@@ -170,7 +174,8 @@ trips_status trips_export_fragments(const trips_config* cfg_host, const trips_ca
 
 /* Statistics of the forward call that filled `saved`, copied to host memory after a
    stream synchronisation: stats_host[0] = tile entries, [1] = work items (tile pieces of
-   at most item_entries entries, and tiles of at most 256 entries, which are rendered whole),
+   at most item_entries entries, and tiles of at most 256 entries, which are rendered whole;
+   with include_coarser only empty tiles are rendered whole),
    [2] = tiles (bins), [3] = (point, view) pairs that wrote at least one fragment.
    For tests and reports; not needed for rendering. */
 trips_status trips_forward_stats(const trips_config* cfg_host, const trips_camera* cams_host,
