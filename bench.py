@@ -1,7 +1,7 @@
 """Benchmark: splatted points per second for forward+backward trilinear point splatting.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                [--no-coarser]
+                [--no-coarser] [--no-optim]
 
 Workload (one step = the whole hot path once): 2M points drawn from 64 anisotropic Gaussian
 clusters plus 30% on planar patches, one 1920x1080 pinhole view, 8 pyramid layers,
@@ -17,8 +17,8 @@ it.  Also reported: per-kernel durations
 (a second timed run of eager steps with HIP events around every launch, on its stream), the
 roofline of the dominant kernel, the CPU oracle on the same workload, and the batched
 multi-view form (16 views of mixed resolution over 4M points, one graph launch per step)
-against 16 single-view launch sequences, and the same workload with coarser-layer
-inclusion in blending.
+against 16 single-view launch sequences, the same workload with coarser-layer inclusion in
+blending, and the optimisation loop (8M points, 8 views of 2560x1440, D = 8, fwd + bwd + Adam).
 """
 import argparse
 import json
@@ -165,6 +165,63 @@ def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev):
                           if k in stage_ms}}
 
 
+def run_optimisation(torch, tp, scenes, iters, warmup, dev):
+    """The optimisation workload: 8M points, 8 views of 2560x1440 in one batched call, 8
+    layers, D = 8; each iteration renders through the autograd function, takes the weighted
+    squared error against target pyramids, back-propagates and steps Adam on positions,
+    log-sizes, opacities and descriptors.  The targets (of a perturbed copy: positions +
+    N(0, 0.01^2), sizes x U[0.5, 2]) are rendered by this renderer, since the CPU oracle would
+    take minutes at this size; the small-size version of the loop uses oracle targets."""
+    import numpy as np
+    sc = scenes.ring_scene(5)
+    pts, cams, nl, D = sc["points"], sc["cams"], sc["nlayers"], sc["D"]
+    n = len(pts["x"])
+    r = tp.Renderer(cams, nl, D, n, device=dev)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    truth = scenes.perturbed(pts, seed=55)
+    with torch.no_grad():
+        target = r.forward(*[dv(truth[k]) for k in PARAMS]).clone()
+    wts = []
+    for c in cams:
+        dims, _ = tp.layer_layout(c, nl)
+        for (w, h) in dims:
+            wts.append(torch.full((w * h * D,), 1.0 / (w * h * D), device=dev))
+    wts = torch.cat(wts)
+    xyz = [dv(pts[k]).requires_grad_(True) for k in ("x", "y", "z")]
+    log_sw = torch.log(dv(pts["sw"])).requires_grad_(True)
+    alpha = dv(pts["alpha"]).requires_grad_(True)
+    desc = dv(pts["desc"]).requires_grad_(True)
+    opt = torch.optim.Adam([{"params": xyz, "lr": 1e-4}, {"params": [log_sw], "lr": 1e-2},
+                            {"params": [desc], "lr": 1e-2}, {"params": [alpha], "lr": 1e-2}])
+    losses = []
+
+    def step():
+        opt.zero_grad()
+        out = tp.render(*xyz, torch.exp(log_sw), alpha, desc, r)
+        loss = ((out - target) ** 2 * wts).sum()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            alpha.clamp_(0.0, 1.0)
+        return loss
+
+    for _ in range(warmup):
+        losses.append(step().item())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    last = None
+    for _ in range(iters):
+        last = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    return {"workload": "ring8m_8views_2560x1440_8layers_d8_fwd_bwd_adam", "points": n,
+            "views": len(cams), "iterations": iters, "ms_per_iteration": ms,
+            "point_views_per_s": n * len(cams) / (ms / 1e3),
+            "loss_first": losses[0] if losses else None, "loss_last": last.item()}
+
+
 def run_batched(torch, tp, scenes, steps, warmup, dev):
     """16 views of mixed resolution over 4M points: one batched forward+backward per step (as a
     graph launch and as direct launches; the faster counts) vs 16 single-view forward+backward
@@ -229,6 +286,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-coarser", action="store_true")
+    ap.add_argument("--no-optim", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference for "
                          "scaling HBM byte counters) and exit")
@@ -359,6 +417,10 @@ def main():
         log("batched vs per-view (16 views, 4M points)")
         out["batched"] = run_batched(torch, tp, scenes, max(3, args.steps // 4),
                                      max(1, args.warmup // 2), dev)
+    if not args.no_optim:
+        log("optimisation loop (8M points, 8 views of 2560x1440, D = 8)")
+        out["optimisation"] = run_optimisation(torch, tp, scenes, max(3, args.steps // 4),
+                                               max(1, args.warmup // 2), dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one step)")
         out["cpu_baseline"] = cpu_baseline(sc, Gnp)
