@@ -165,6 +165,34 @@ def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev):
                           if k in stage_ms}}
 
 
+def run_points_8m(torch, tp, scenes, steps, warmup, dev):
+    """The headline recipe with 8M points (1920x1080, 8 layers, D = 4, forward + backward),
+    launched directly."""
+    sc = scenes.cluster_scene(2, n=8_000_000)
+    cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
+    n = len(sc["points"]["x"])
+    t = {k: torch.from_numpy(sc["points"][k]).to(dev) for k in PARAMS}
+    args = [t[k] for k in PARAMS]
+    r = tp.Renderer([cam], nl, D, n, device=dev)
+    G = torch.from_numpy(scenes.upstream_gradient(3, r.pyramid_numel())).to(dev)
+    pyr = torch.empty(r.pyramid_numel(), device=dev)
+    grads = [torch.empty(n, device=dev) for _ in range(5)] + [torch.empty((n, D), device=dev)]
+    for _ in range(warmup):
+        r.forward(*args, out=pyr)
+        r.backward(*args, G, outs=grads)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        r.forward(*args, out=pyr)
+        r.backward(*args, G, outs=grads)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": "clusters8m_1920x1080_8layers_d4_fwd_bwd", "points": n,
+            "ms_per_step": ms, "points_per_s": n / (ms / 1e3)}
+
+
 def run_optimisation(torch, tp, scenes, iters, warmup, dev):
     """The optimisation workload: 8M points, 8 views of 2560x1440 in one batched call, 8
     layers, D = 8; each iteration renders through the autograd function, takes the weighted
@@ -418,6 +446,9 @@ def main():
         out["batched"] = run_batched(torch, tp, scenes, max(3, args.steps // 4),
                                      max(1, args.warmup // 2), dev)
     if not args.no_optim:
+        log("8M points at 1080p")
+        out["points_8m"] = run_points_8m(torch, tp, scenes, max(3, args.steps // 2),
+                                         max(1, args.warmup // 2), dev)
         log("optimisation loop (8M points, 8 views of 2560x1440, D = 8)")
         out["optimisation"] = run_optimisation(torch, tp, scenes, max(3, args.steps // 4),
                                                max(1, args.warmup // 2), dev)
