@@ -1365,7 +1365,10 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   constexpr int EB = 2;  // entries per thread in flight
   __shared__ uint32_t s_k[TP];
   __shared__ uint64_t s_last[TP];
-  __shared__ uint4 s_idx[TP][KEEP / 4];  // kept point ids of each texel, contiguous
+  // kept point ids, four per 16 bytes, quarter-list major: the reads of one quarter by lanes
+  // of random texels then fall on eight bank groups rather than two (texel-major rows are
+  // 64 bytes apart)
+  __shared__ uint4 s_idx[KEEP / 4][TP];
   __shared__ float s_G[TP][D + 1];
   const int t = threadIdx.x;
   const uint32_t total = info[1];
@@ -1402,7 +1405,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
       last = uint32_t(m) < k ? key : last;
     }
 #pragma unroll
-    for (int m = 0; m < KEEP; m += 4) s_idx[t][m / 4] = make_uint4(ids[m], ids[m + 1], ids[m + 2], ids[m + 3]);
+    for (int m = 0; m < KEEP; m += 4) s_idx[m / 4][t] = make_uint4(ids[m], ids[m + 1], ids[m + 2], ids[m + 3]);
     s_last[t] = last;
     const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
     const int j = (bi.ty << lth) + (t >> P.ltw);
@@ -1440,7 +1443,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
         if (kp != 0 && !(key > s_last[p])) {  // among the kept fragments: find its position
 #pragma unroll
           for (int j = 0; j < KEEP / 4; ++j) {
-            const uint4 v = s_idx[p][j];
+            const uint4 v = s_idx[j][p];
             m = (v.x == en[h].idx && uint32_t(4 * j) < kp) ? uint32_t(4 * j) : m;
             m = (v.y == en[h].idx && uint32_t(4 * j + 1) < kp) ? uint32_t(4 * j + 1) : m;
             m = (v.z == en[h].idx && uint32_t(4 * j + 2) < kp) ? uint32_t(4 * j + 2) : m;
