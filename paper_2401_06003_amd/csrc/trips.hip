@@ -384,12 +384,81 @@ __global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const flo
     row[i] = (hist[i >> 1] >> ((i & 1u) * 16u)) & 0xffffu;
 }
 
-// colscan: per bin, exclusive prefix of H over point blocks (in place) and the bin total.
-// Workgroup = 64 bins x 16 block segments.
+// The tile scan over chunks of 64 tiles (one wavefront each): the chunk sums (written by the
+// column scan, whose workgroups cover the same chunks), then two short passes.  A tile
+// of at most FINE_E entries is listed in fine_work; every other tile is listed in coarse_bins
+// and cut into ceil(total / item_e) work items; tiles with more than one item are listed in
+// multi_bins (their partial lists are merged).  bin_start and item_start are the exclusive
+// scans of entries and items.
+constexpr uint32_t CHUNK = 64;
+constexpr int CSUM = 4 + NBUCKET;  // per chunk: entries, items, multi tiles, fine tiles, classes
+
+// ceil(a / b) for b > 0: the correctly rounded double quotient of integers below 2^33 is
+// never rounded across an integer (a quotient just below k is at least 1/b below it), so its
+// ceiling is exact.
+__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) {
+  return uint32_t(ceil(double(a) / double(b)));
+}
+
+struct TileCount { uint32_t e, it, multi, fine; };
+__device__ __forceinline__ TileCount tile_count_of(uint32_t e, bool valid, uint32_t item_e,
+                                                   uint32_t fine_e) {
+  TileCount r{0u, 0u, 0u, 0u};
+  if (valid) {
+    r.e = e;
+    r.fine = r.e <= fine_e ? 1u : 0u;
+    r.it = r.fine ? 0u : ceil_div(r.e, item_e);
+    r.multi = r.it > 1 ? 1u : 0u;
+  }
+  return r;
+}
+__device__ __forceinline__ TileCount tile_count(const uint32_t* __restrict__ tot, uint32_t b,
+                                                uint32_t NB, uint32_t item_e, uint32_t fine_e) {
+  return tile_count_of(b < NB ? tot[b] : 0u, b < NB, item_e, fine_e);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// The sums of one chunk (a wavefront, a tile per lane): entries, items, multi-item tiles,
+// fine tiles and the items per size class; lane 0 writes them.
+__device__ __forceinline__ void chunk_sums(const TileCount& c, uint32_t item_e,
+                                           uint32_t* __restrict__ out) {
+  // it - 1 items of item_e entries (class 0) and a last one of the rest
+  const uint32_t cls = c.it ? size_class(c.e - (c.it - 1) * item_e, item_e) : 0u;
+  uint32_t v[CSUM];
+  v[0] = c.e; v[1] = c.it; v[2] = c.multi; v[3] = c.fine;
+#pragma unroll
+  for (int q = 0; q < NBUCKET; ++q)
+    v[4 + q] = (q == 0 && c.it ? c.it - 1 : 0u) + (c.it && cls == uint32_t(q) ? 1u : 0u);
+#pragma unroll
+  for (int q = 0; q < CSUM; ++q) {
+    const uint32_t w = wave_sum_u32(v[q]);
+    if ((threadIdx.x & 63) == 0) out[q] = w;
+  }
+}
+
+// chunksum: the chunk sums from the tile totals (used when there are no points, so the
+// column scan, which otherwise writes them, does not run).
+__global__ __launch_bounds__(64) void k_chunksum(const uint32_t* __restrict__ tot,
+                                                 uint32_t* __restrict__ csum, uint32_t NB,
+                                                 uint32_t item_e, uint32_t fine_e) {
+  const uint32_t b = blockIdx.x * CHUNK + threadIdx.x;
+  chunk_sums(tile_count(tot, b, NB, item_e, fine_e), item_e, csum + size_t(blockIdx.x) * CSUM);
+}
+
+// colscan: per bin, exclusive prefix of H over point blocks (in place) and the bin total;
+// the wavefront that finishes the totals of its 64 bins (one chunk) also writes the chunk's
+// sums.  Workgroup = 64 bins x 16 block segments.
 constexpr int CS_SEG = 16;
+static_assert(CHUNK == 64, "a column-scan workgroup covers one chunk");
 __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ H,
                                                          uint32_t* __restrict__ tot, uint32_t NB,
-                                                         uint32_t nblk) {
+                                                         uint32_t nblk, uint32_t* __restrict__ csum,
+                                                         uint32_t item_e, uint32_t fine_e) {
   __shared__ uint32_t ssum[CS_SEG][64];
   const uint32_t lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
   const uint32_t b = blockIdx.x * 64 + lane;
@@ -411,6 +480,9 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
   __syncthreads();
   uint32_t run = 0;
   for (uint32_t s = 0; s < seg; ++s) run += ssum[s][lane];
+  if (seg == CS_SEG - 1)  // the whole wavefront (lanes past NB count nothing)
+    chunk_sums(tile_count_of(run + sum, b < NB, item_e, fine_e), item_e,
+               csum + size_t(blockIdx.x) * CSUM);
   if (b < NB) {
     if (seg == CS_SEG - 1) tot[b] = run + sum;
     for (uint32_t k = k0; k < k1; k += RB) {
@@ -424,60 +496,6 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
           run += v[q];
         }
     }
-  }
-}
-
-// The tile scan in three short passes over chunks of 64 tiles (one wavefront each).  A tile
-// of at most FINE_E entries is listed in fine_work; every other tile is listed in coarse_bins
-// and cut into ceil(total / item_e) work items; tiles with more than one item are listed in
-// multi_bins (their partial lists are merged).  bin_start and item_start are the exclusive
-// scans of entries and items.
-constexpr uint32_t CHUNK = 64;
-constexpr int CSUM = 4 + NBUCKET;  // per chunk: entries, items, multi tiles, fine tiles, classes
-
-// ceil(a / b) for b > 0: the correctly rounded double quotient of integers below 2^33 is
-// never rounded across an integer (a quotient just below k is at least 1/b below it), so its
-// ceiling is exact.
-__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) {
-  return uint32_t(ceil(double(a) / double(b)));
-}
-
-struct TileCount { uint32_t e, it, multi, fine; };
-__device__ __forceinline__ TileCount tile_count(const uint32_t* __restrict__ tot, uint32_t b,
-                                                uint32_t NB, uint32_t item_e, uint32_t fine_e) {
-  TileCount r{0u, 0u, 0u, 0u};
-  if (b < NB) {
-    r.e = tot[b];
-    r.fine = r.e <= fine_e ? 1u : 0u;
-    r.it = r.fine ? 0u : ceil_div(r.e, item_e);
-    r.multi = r.it > 1 ? 1u : 0u;
-  }
-  return r;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-// chunksum: per chunk, the four sums and the items per size class.
-__global__ __launch_bounds__(64) void k_chunksum(const uint32_t* __restrict__ tot,
-                                                 uint32_t* __restrict__ csum, uint32_t NB,
-                                                 uint32_t item_e, uint32_t fine_e) {
-  const uint32_t b = blockIdx.x * CHUNK + threadIdx.x;
-  const TileCount c = tile_count(tot, b, NB, item_e, fine_e);
-  // it - 1 items of item_e entries (class 0) and a last one of the rest
-  const uint32_t cls = c.it ? size_class(c.e - (c.it - 1) * item_e, item_e) : 0u;
-  uint32_t v[CSUM];
-  v[0] = c.e; v[1] = c.it; v[2] = c.multi; v[3] = c.fine;
-#pragma unroll
-  for (int q = 0; q < NBUCKET; ++q)
-    v[4 + q] = (q == 0 && c.it ? c.it - 1 : 0u) + (c.it && cls == uint32_t(q) ? 1u : 0u);
-#pragma unroll
-  for (int q = 0; q < CSUM; ++q) {
-    const uint32_t w = wave_sum_u32(v[q]);
-    if (threadIdx.x == 0) csum[size_t(blockIdx.x) * CSUM + q] = w;
   }
 }
 
@@ -2482,6 +2500,9 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   const Params& P = lay.P;
   uint32_t* H = reinterpret_cast<uint32_t*>(ws + lay.w_H);
   uint32_t* tot = reinterpret_cast<uint32_t*>(ws + lay.w_tot);
+  const uint32_t nch = (P.NB + CHUNK - 1) / CHUNK;
+  uint32_t* csum = reinterpret_cast<uint32_t*>(ws + lay.w_csum);
+  uint32_t* coff = reinterpret_cast<uint32_t*>(ws + lay.w_coff);
   uint32_t* pcnt = reinterpret_cast<uint32_t*>(ws + lay.w_pcnt);
   uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + lay.w_pkey);
   float* pgam = reinterpret_cast<float*>(ws + lay.w_pgam);
@@ -2506,20 +2527,18 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_COLSCAN, st);
-    if (P.nblk > 0)
+    if (P.nblk > 0) {  // also writes the chunk sums
       hipLaunchKernelGGL(k_colscan, dim3((P.NB + 63) / 64), dim3(64 * CS_SEG), 0, st, H, tot,
-                         P.NB, P.nblk);
-    else
+                         P.NB, P.nblk, csum, P.item_e, P.fine_e);
+    } else {
       hipLaunchKernelGGL(k_fill_u32, dim3((P.NB + 255) / 256), dim3(256), 0, st, tot, P.NB, 0u);
+      hipLaunchKernelGGL(k_chunksum, dim3(nch), dim3(CHUNK), 0, st, tot, csum, P.NB, P.item_e,
+                         P.fine_e);
+    }
   }
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BINSCAN, st);
-    const uint32_t nch = (P.NB + CHUNK - 1) / CHUNK;
-    uint32_t* csum = reinterpret_cast<uint32_t*>(ws + lay.w_csum);
-    uint32_t* coff = reinterpret_cast<uint32_t*>(ws + lay.w_coff);
-    hipLaunchKernelGGL(k_chunksum, dim3(nch), dim3(CHUNK), 0, st, tot, csum, P.NB, P.item_e,
-                       P.fine_e);
     hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, st, csum, coff, bin_start, item_start,
                        info, P.NB, nch);
     hipLaunchKernelGGL(k_binscan, dim3(nch), dim3(CHUNK), 0, st, tot, coff, bin_start, item_start,
