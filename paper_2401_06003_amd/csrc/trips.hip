@@ -562,7 +562,13 @@ __global__ __launch_bounds__(1024) void k_chunkscan(const uint32_t* __restrict__
 // every item writes its own outputs).  A slot describes item it as
 // {tile, first entry, end entry, it | (tile has several items) << 31}; slots are reserved per
 // chunk and class, with LDS counters and then one global atomic per class.
+// With FUSED (at most FUSE_CHUNKS chunks), every wavefront instead derives its chunk's
+// offsets, and the first slot of each class, from the chunk sums of all chunks (the chunk
+// scan does not run), and wavefront 0 writes the totals.
+constexpr uint32_t FUSE_CHUNKS = 512;
+template <bool FUSED>
 __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot,
+                                                const uint32_t* __restrict__ csum,
                                                 const uint32_t* __restrict__ coff,
                                                 uint32_t* __restrict__ bin_start,
                                                 uint32_t* __restrict__ item_start,
@@ -570,13 +576,61 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
                                                 uint4* __restrict__ fine_work,
                                                 uint32_t* __restrict__ coarse_bins,
                                                 uint32_t* __restrict__ info, uint4* __restrict__ work,
-                                                uint32_t NB, uint32_t item_e, uint32_t fine_e) {
+                                                uint32_t NB, uint32_t nch, uint32_t item_e,
+                                                uint32_t fine_e) {
   __shared__ uint32_t s_cnt[NBUCKET], s_base[NBUCKET];
   const int t = threadIdx.x;
   if (t < NBUCKET) s_cnt[t] = 0;
   const uint32_t b = blockIdx.x * CHUNK + t;
   const TileCount c = tile_count(tot, b, NB, item_e, fine_e);
-  const uint32_t* co = coff + size_t(blockIdx.x) * 4;
+  uint32_t co[4];
+  if (FUSED) {
+    uint32_t pre[CSUM], all[CSUM];  // sums over the chunks before this one, over all chunks
+#pragma unroll
+    for (int q = 0; q < CSUM; ++q) pre[q] = all[q] = 0u;
+    for (uint32_t k = t; k < nch; k += 64) {
+      const uint32_t* r = csum + size_t(k) * CSUM;
+      const bool before = k < blockIdx.x;
+#pragma unroll
+      for (int q = 0; q < CSUM; ++q) {
+        const uint32_t x = r[q];
+        all[q] += x;
+        pre[q] += before ? x : 0u;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CSUM; ++q) {
+      pre[q] = wave_sum_u32(pre[q]);
+      all[q] = wave_sum_u32(all[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) co[q] = pre[q];
+    const bool lead = blockIdx.x == 0 && t == 0;
+    uint32_t o = 0;
+#pragma unroll
+    for (int q = 0; q < NBUCKET; ++q) {
+      if (t == 0) s_base[q] = o + pre[4 + q];
+      if (lead) {
+        info[INFO_BUCKET + q] = o;
+        info[INFO_BUCKET + NBUCKET + q] = 0;
+      }
+      o += all[4 + q];
+    }
+    if (lead) {
+      bin_start[NB] = all[0];
+      item_start[NB] = all[1];
+      info[0] = all[0];
+      info[1] = all[1];
+      info[2] = 0;  // visible (point, view) pairs, accumulated by the scatter pass
+      info[3] = all[2];
+      info[4] = all[3];
+      info[5] = NB - all[3];
+    }
+  } else {
+    const uint32_t* cp = coff + size_t(blockIdx.x) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) co[q] = cp[q];
+  }
   const uint32_t oe = co[0] + wave_incl_scan(c.e) - c.e;
   const uint32_t oi = co[1] + wave_incl_scan(c.it) - c.it;
   const uint32_t om = co[2] + wave_incl_scan(c.multi) - c.multi;
@@ -596,7 +650,7 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
   const uint32_t rf = nfull ? atomicAdd(&s_cnt[0], nfull) : 0u;
   const uint32_t rl = c.it ? atomicAdd(&s_cnt[q], 1u) : 0u;
   __syncthreads();
-  if (t < NBUCKET && s_cnt[t])
+  if (!FUSED && t < NBUCKET && s_cnt[t])
     s_base[t] = info[INFO_BUCKET + t] + atomicAdd(&info[INFO_BUCKET + NBUCKET + t], s_cnt[t]);
   __syncthreads();
   if (!c.it) return;
@@ -2539,10 +2593,17 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_BINSCAN, st);
-    hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, st, csum, coff, bin_start, item_start,
-                       info, P.NB, nch);
-    hipLaunchKernelGGL(k_binscan, dim3(nch), dim3(CHUNK), 0, st, tot, coff, bin_start, item_start,
-                       multi_bins, fine_work, coarse_bins, info, work, P.NB, P.item_e, P.fine_e);
+    if (nch <= FUSE_CHUNKS) {
+      hipLaunchKernelGGL(k_binscan<true>, dim3(nch), dim3(CHUNK), 0, st, tot, csum, coff,
+                         bin_start, item_start, multi_bins, fine_work, coarse_bins, info, work,
+                         P.NB, nch, P.item_e, P.fine_e);
+    } else {
+      hipLaunchKernelGGL(k_chunkscan, dim3(1), dim3(1024), 0, st, csum, coff, bin_start,
+                         item_start, info, P.NB, nch);
+      hipLaunchKernelGGL(k_binscan<false>, dim3(nch), dim3(CHUNK), 0, st, tot, csum, coff,
+                         bin_start, item_start, multi_bins, fine_work, coarse_bins, info, work,
+                         P.NB, nch, P.item_e, P.fine_e);
+    }
   }
   TRIPS_HIP(hipGetLastError());
   if (P.nblk > 0) {
