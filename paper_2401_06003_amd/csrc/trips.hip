@@ -906,8 +906,13 @@ __device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
 // entries into fragments, counting-sorts them by texel and lets the thread owning the texel
 // insert them into its register top-16; in the first round, whose lists are all empty, the
 // fragments' depth ranks are counted in LDS instead and the first 16 ranks loaded in order.
-// A fragment whose key is not below the texel's current 16th key is only counted, never
-// sorted.
+// A fragment whose depth bits are above those of the texel's current 16th key is only
+// counted, never sorted (the insertion makes the exact comparison).  A texel's tally and its
+// count of sorted fragments share one LDS word, so a fragment costs one LDS atomic.
+constexpr uint32_t TALLY_BITS = 20;  // per-texel word: all fragments of the item (low bits),
+constexpr uint32_t TALLY_MASK = (1u << TALLY_BITS) - 1u;  // and this round's sorted ones or
+                                                          // the start of the texel's run
+static_assert(4u * SUB_E < (1u << (32 - TALLY_BITS)), "run starts fit the high bits");
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_items(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
@@ -915,14 +920,16 @@ __global__ __launch_bounds__(256) void k_fwd_items(
     uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam,
     uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey, float* __restrict__ pgam,
     const float* __restrict__ bg, float* __restrict__ alpha) {
-  __shared__ uint32_t hist[TP];    // sorted fragments per texel in this round, then run starts
-  __shared__ uint32_t tally[TP];   // all fragments per texel in this item
-  __shared__ uint64_t thr[TP];     // current 16th key per texel
-  __shared__ uint32_t ws[4];
+  __shared__ uint32_t th[TP];      // tally | (sorted fragments, then run start) << TALLY_BITS
+  __shared__ uint32_t thz[TP];     // depth bits of the current 16th key per texel
   __shared__ uint64_t skey[SUB_F];
   __shared__ float sgam[SUB_F];
   __shared__ uint8_t stex[SUB_F];   // texel of each sorted fragment (first round)
-  __shared__ uint16_t sord[SUB_F];  // at run start + r: run position of rank r (first round)
+  // at run start + r: run position of rank r (first round); its first words also serve the
+  // run-start scan, which is done with them before the first round writes ranks
+  __shared__ uint32_t sord_w[SUB_F / 2];
+  uint16_t* sord = reinterpret_cast<uint16_t*>(sord_w);
+  uint32_t* ws = sord_w;
   const int t = threadIdx.x;
   const uint32_t total = info[1];
   const uint4 wk = work[blockIdx.x];  // in bounds (grid = capacity); used only if valid
@@ -934,15 +941,15 @@ __global__ __launch_bounds__(256) void k_fwd_items(
   float kg[KEEP];
 #pragma unroll
   for (int m = 0; m < KEEP; ++m) { kk[m] = KEY_NONE; kg[m] = 0.0f; }
-  tally[t] = 0;
-  thr[t] = KEY_NONE;
+  th[t] = 0;
+  thz[t] = ~0u;
   // entries of the current round, loaded one round ahead
   Entry en[EPT];
 #pragma unroll
   for (int q = 0; q < EPT; ++q)
     if (e0 + q * TP + t < e1) en[q] = ent[e0 + q * TP + t];
   for (uint32_t s0 = e0; s0 < e1; s0 += SUB_E) {
-    hist[t] = 0;
+    th[t] &= TALLY_MASK;
     __syncthreads();
     uint32_t cm[EPT], rank[EPT][2];  // corner masks; 16-bit ranks, two per word
 #pragma unroll
@@ -951,13 +958,13 @@ __global__ __launch_bounds__(256) void k_fwd_items(
       rank[q][0] = rank[q][1] = 0;
       Corner cs[4];
       if (s0 + q * TP + t < e1) cm[q] = entry_corners(en[q], bi, P.ltw, cs);
-      const uint64_t key = (uint64_t(en[q].zbits) << 32) | en[q].idx;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if ((cm[q] >> c) & 1u) {
           const int px = cs[c].p;
-          atomicAdd(&tally[px], 1u);
-          if (key < thr[px]) rank[q][c >> 1] |= atomicAdd(&hist[px], 1u) << ((c & 1) * 16);
+          const bool pass = en[q].zbits <= thz[px];
+          const uint32_t old = atomicAdd(&th[px], pass ? 1u + (1u << TALLY_BITS) : 1u);
+          if (pass) rank[q][c >> 1] |= (old >> TALLY_BITS) << ((c & 1) * 16);
           else cm[q] &= ~(1u << c);
         }
       }
@@ -967,10 +974,10 @@ __global__ __launch_bounds__(256) void k_fwd_items(
     for (int q = 0; q < EPT; ++q)
       if (s0 + SUB_E + q * TP + t < e1) nx[q] = ent[s0 + SUB_E + q * TP + t];
     __syncthreads();
-    const uint32_t cnt = hist[t];
+    const uint32_t cnt = th[t] >> TALLY_BITS;
     uint32_t tot;
     const uint32_t base = block_excl_scan<4>(cnt, ws, tot);
-    hist[t] = base;  // all counts were read before the scan's first barrier
+    th[t] = (th[t] & TALLY_MASK) | (base << TALLY_BITS);  // counts were read before the scan
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -981,7 +988,8 @@ __global__ __launch_bounds__(256) void k_fwd_items(
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         if ((cm[q] >> c) & 1u) {
-          const uint32_t o = hist[cs[c].p] + ((rank[q][c >> 1] >> ((c & 1) * 16)) & 0xffffu);
+          const uint32_t o =
+              (th[cs[c].p] >> TALLY_BITS) + ((rank[q][c >> 1] >> ((c & 1) * 16)) & 0xffffu);
           skey[o] = key;
           sgam[o] = (cs[c].wx * cs[c].wy) * en[q].ia;
           stex[o] = uint8_t(cs[c].p);
@@ -994,7 +1002,8 @@ __global__ __launch_bounds__(256) void k_fwd_items(
       // distinct in a texel), then each thread loads its first 16 ranks in order.
       for (uint32_t o = t; o < tot; o += TP) {
         const uint32_t p = stex[o];
-        const uint32_t r0 = hist[p], r1 = p + 1 < TP ? hist[p + 1] : tot;
+        const uint32_t r0 = th[p] >> TALLY_BITS;
+        const uint32_t r1 = p + 1 < TP ? th[p + 1] >> TALLY_BITS : tot;
         const uint64_t ko = skey[o];
         uint32_t rk = 0;
         for (uint32_t r = r0; r < r1; r += 4) {
@@ -1030,12 +1039,12 @@ __global__ __launch_bounds__(256) void k_fwd_items(
         for (int q = 0; q < 4; ++q) top_insert(kk, kg, rk[q], rg[q]);
       }
     }
-    thr[t] = kk[KEEP - 1];
+    thz[t] = uint32_t(kk[KEEP - 1] >> 32);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) en[q] = nx[q];
     __syncthreads();
   }
-  const uint32_t n = tally[t];
+  const uint32_t n = th[t] & TALLY_MASK;
   if (!multi) {
     finalize_texel<D>(P, bi, b, kk, kg, n, desc, pyr, npix, kkey, kgam, bg, alpha, t);
   } else {
