@@ -189,8 +189,16 @@ def run_points_8m(torch, tp, scenes, steps, warmup, dev):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    tp.timing_enable(True)
+    for _ in range(steps):
+        r.forward(*args, out=pyr)
+        r.backward(*args, G, outs=grads)
+    torch.cuda.synchronize()
+    stages = tp.timing_read()
+    tp.timing_enable(False)
+    stage_ms = {k: round(v[0] / max(v[1], 1), 5) for k, v in stages.items() if v[1] > 0}
     return {"workload": "clusters8m_1920x1080_8layers_d4_fwd_bwd", "points": n,
-            "ms_per_step": ms, "points_per_s": n / (ms / 1e3)}
+            "ms_per_step": ms, "points_per_s": n / (ms / 1e3), "stage_ms": stage_ms}
 
 
 def run_optimisation(torch, tp, scenes, iters, warmup, dev):
