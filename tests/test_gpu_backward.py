@@ -57,7 +57,7 @@ def test_descriptor_width_8(gpu):
 
 
 def test_matches_central_differences(gpu):
-    """The spec bar: GPU gradients within 1e-3 of FP64 central differences."""
+    """The gradient accuracy bar: GPU gradients within 1e-3 of FP64 central differences."""
     seed, sc = _fd_scene()
     cam, n = sc["cams"][0], sc["nlayers"]
     P = oracle.num_pixels(cam["W"], cam["H"], n)
