@@ -76,10 +76,11 @@ def step_bytes(N, Nv, D, F, K, P):
     return N * 20 + Nv * 4 * D + 16 * F + 8 * K + 8 * D * P + Nv * (20 + 4 * D) + N * (20 + 4 * D)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, field="bytes_per_launch"):
     """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE passes, each scaled by the same counter over a plain copy), or None when no
-    summary was taken on the current kernel source."""
+    WRITE_SIZE passes, each scaled by the same counter over a plain copy), or, with
+    field="step_bytes", those of every kernel of one step; None when no summary was taken on
+    the current kernel source."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2401_06003_amd", "csrc", "trips.hip")
@@ -89,7 +90,7 @@ def measured_traffic(kernel):
             if line.startswith("traffic-json: "):
                 d = json.loads(line[len("traffic-json: "):])
                 if d.get("kernel") == kernel and d.get("source_sha256") == h:
-                    return d["bytes_per_launch"]
+                    return d.get(field)
     return None
 
 
@@ -425,6 +426,7 @@ def main():
     achieved = dom_bytes / (stage_ms[dom] / 1e3) / 1e9
     sbytes = step_bytes(N, Nv, D, F, K, P)
 
+    step_meas = measured_traffic(dom, "step_bytes")
     out = {
         "metric": METRIC, "value": N / (ms / 1e3), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -439,6 +441,9 @@ def main():
         "ms_per_step_eager_with_kernel_events": ms_events,
         "step_effective_hbm_frac": sbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "step_algorithmic_bytes": sbytes,
+        "step_measured_hbm_bytes": step_meas,
+        "step_achieved_hbm_frac": (step_meas / (ms / 1e3) / 1e9 / HBM_PEAK_GBS
+                                   if step_meas else None),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "fragments": F, "kept_fragments": K, "tile_entries": E, "tiles": NB, "texels": P,
         "visible_points": Nv, "fine_tiles": w["NB_f"], "fine_tile_entries": w["E_f"],
