@@ -329,8 +329,9 @@ def main():
                          "scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this renderer runs on one GPU; multi-GPU runs are not part of this "
-              "build (views would shard across GPUs with one gradient all-reduce).", flush=True)
+        print("bench.py: this renderer runs on one GPU; runs over several GPUs are not "
+              "implemented (views would shard across GPUs with one gradient all-reduce).",
+              flush=True)
         sys.exit(2)
 
     import numpy as np
