@@ -464,11 +464,20 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
   const uint32_t b = blockIdx.x * 64 + lane;
   const uint32_t per = (nblk + CS_SEG - 1) / CS_SEG;
   const uint32_t k0 = min(nblk, seg * per), k1 = min(nblk, k0 + per);
-  // rows are read eight at a time (independent loads; rows past the segment read its last
-  // row, a valid address, and are not used)
-  constexpr uint32_t RB = 8;
+  // A segment of at most RC rows is read once, all rows at a time, and kept in registers for
+  // the prefix pass; longer segments are read eight rows at a time, twice.  Rows past the
+  // segment read its last row (a valid address) and are not used.
+  constexpr uint32_t RB = 8, RC = 32;
+  const bool cached = per <= RC;  // uniform over the workgroup
+  uint32_t c[RC];
   uint32_t sum = 0;
-  if (b < NB)
+  if (cached) {
+    const uint32_t bb = min(b, NB - 1);
+#pragma unroll
+    for (uint32_t q = 0; q < RC; ++q) c[q] = H[size_t(min(k0 + q, k1 - 1)) * NB + bb];
+#pragma unroll
+    for (uint32_t q = 0; q < RC; ++q) sum += k0 + q < k1 && b < NB ? c[q] : 0u;
+  } else if (b < NB) {
     for (uint32_t k = k0; k < k1; k += RB) {
       uint32_t v[RB];
 #pragma unroll
@@ -476,6 +485,7 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
 #pragma unroll
       for (uint32_t q = 0; q < RB; ++q) sum += k + q < k1 ? v[q] : 0u;
     }
+  }
   ssum[seg][lane] = sum;
   __syncthreads();
   uint32_t run = 0;
@@ -483,7 +493,15 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
   if (seg == CS_SEG - 1)  // the whole wavefront (lanes past NB count nothing)
     chunk_sums(tile_count_of(run + sum, b < NB, item_e, fine_e), item_e,
                csum + size_t(blockIdx.x) * CSUM);
-  if (b < NB) {
+  if (b < NB && cached) {
+    if (seg == CS_SEG - 1) tot[b] = run + sum;
+#pragma unroll
+    for (uint32_t q = 0; q < RC; ++q)
+      if (k0 + q < k1) {
+        H[size_t(k0 + q) * NB + b] = run;
+        run += c[q];
+      }
+  } else if (b < NB) {
     if (seg == CS_SEG - 1) tot[b] = run + sum;
     for (uint32_t k = k0; k < k1; k += RB) {
       uint32_t v[RB];
