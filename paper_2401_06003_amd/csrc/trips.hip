@@ -706,18 +706,21 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
   const uint32_t* bs = bin_start + c.bin_base;
   if (threadIdx.x == 0) s_vis = 0;
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) hist[i] = 0;
-  if (STAGED)  // four bins per thread in flight
-    for (uint32_t i0 = threadIdx.x; i0 < c.nbins; i0 += 4 * blockDim.x) {
-      uint32_t v4[4];
+  if (STAGED) {  // SB bins per thread in flight (a 1080p view's tiles in one batch)
+    constexpr int SB = 12;
+    for (uint32_t i0 = threadIdx.x; i0 < c.nbins; i0 += SB * blockDim.x) {
+      uint32_t va[SB], vb[SB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < SB; ++q) {
         const uint32_t i = min(i0 + q * blockDim.x, c.nbins - 1);  // a valid bin, used if in range
-        v4[q] = bs[i] + row[i];
+        va[q] = bs[i];
+        vb[q] = row[i];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (i0 + q * blockDim.x < c.nbins) base[i0 + q * blockDim.x] = v4[q];
+      for (int q = 0; q < SB; ++q)
+        if (i0 + q * blockDim.x < c.nbins) base[i0 + q * blockDim.x] = va[q] + vb[q];
     }
+  }
   __syncthreads();
   const int64_t p0 = int64_t(blk) * P.pb;
   const int64_t p1 = min(P.n, p0 + int64_t(P.pb));
