@@ -173,6 +173,14 @@ def _aligned_bytes(nbytes, device):
     return buf[off:off + max(int(nbytes), 1)]
 
 
+class _SavedState:
+    """Which forward call last wrote a `saved` buffer (shared by renderers that share it)."""
+
+    def __init__(self):
+        self.generation = 0
+        self.owner = None
+
+
 class Renderer:
     """Renders one or more views (different resolutions allowed) of a point cloud.
 
@@ -205,9 +213,11 @@ class Renderer:
             # calls of the two renderers must not overlap on the device (same stream)
             self.workspace, self.saved = o.workspace, o.saved
             self.ws_bytes, self.saved_bytes = o.ws_bytes, o.saved_bytes
+            self._saved_state = o._saved_state
         else:
             self.workspace = _aligned_bytes(self.ws_bytes, self.device)
             self.saved = _aligned_bytes(self.saved_bytes, self.device)
+            self._saved_state = _SavedState()
         self.layouts = [layer_layout(c, num_layers) for c in cams]
         self.view_texels = [lay[1][-1] for lay in self.layouts]
         self.texels = sum(self.view_texels)
@@ -239,6 +249,10 @@ class Renderer:
         self._texel_array(background, self.D, "background")
         self._texel_array(alpha_out, 1, "alpha_out")
         keep, ext = _extras(background=background, alpha_out=alpha_out)
+        # the saved lists now belong to this call: a backward of an earlier forward that used
+        # the same buffer would read them (TripsSplat checks the generation)
+        self._saved_state.generation += 1
+        self._saved_state.owner = self
         _check(lib().trips_forward(ctypes.byref(self.cfg), ctypes.byref(pts), self.cams, self.V,
                                    ctypes.byref(self.tune), _ptr(out), _ptr(self.saved),
                                    self.saved_bytes, _ptr(self.workspace), self.ws_bytes, ext,
@@ -437,12 +451,20 @@ class TripsSplat(torch.autograd.Function):
         args = [t.detach().contiguous() for t in (x, y, z, sw, alpha, desc)]
         out = renderer.forward(*args)
         ctx.renderer = renderer
+        ctx.generation = renderer._saved_state.generation
         ctx.save_for_backward(*args)
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        grads = ctx.renderer.backward(*ctx.saved_tensors, grad_out)
+        r = ctx.renderer
+        st = r._saved_state
+        if st.generation != ctx.generation:
+            raise RuntimeError(
+                "TripsSplat.backward: the renderer's saved fragment lists were overwritten by "
+                "a later forward call (of this renderer or of one sharing its buffers); run "
+                "backward before the next forward, or use one renderer per pending backward")
+        grads = r.backward(*ctx.saved_tensors, grad_out)
         return tuple(grads) + (None,)
 
 

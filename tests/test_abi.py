@@ -151,3 +151,21 @@ def test_autotune_validates_before_launch():
     assert L.trips_autotune(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, bad, 0, 1, fake, fake,
                             1 << 30, fake, 1 << 30, fake, fake, fake, fake, fake, fake, fake,
                             ctypes.byref(best), ms, None) == -1
+
+
+def test_view_with_too_many_tiles_is_unsupported():
+    """The binning passes keep a 16-bit counter per tile of one view in LDS (at most 32768
+    tiles): 3840x2160 with 16x16 tiles over 8 layers has 43,301 and is refused before any
+    launch, as is 3600x1800 (34,116); 3200x1600 (26,704) is accepted."""
+    tp, L = _lib()
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    cfg = tp.make_config(8, 4)
+    for (W, H), code in (((3840, 2160), -5), ((3200, 1600), 0), ((3600, 1800), -5)):
+        cams = (tp.Camera * 1)(tp.make_camera(_cam(W, H)))
+        assert L.trips_buffer_sizes(ctypes.byref(cfg), cams, 1, 1000, None, ctypes.byref(ws),
+                                    ctypes.byref(sv)) == code, (W, H)
+    cams = (tp.Camera * 1)(tp.make_camera(_cam(3840, 2160)))
+    fake = 1 << 20
+    pts = tp.Points(fake, fake, fake, fake, fake, fake, 1000)
+    assert L.trips_forward(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake,
+                           1 << 40, fake, 1 << 40, None, None) == -5

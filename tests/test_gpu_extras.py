@@ -165,17 +165,23 @@ def test_plan_replays_equal_eager(gpu):
 
 
 def test_full_size_coverage_and_camera_gradient(gpu):
-    """The 2M-point 1080p scene with a background: every texel's coverage and the camera
-    gradient (a sum over all points) against the oracle."""
+    """The 2M-point 1080p scene (forward + backward, Sec. 3.1-3.2, Eq. 6-7) with a
+    background, against the oracle evaluated on every texel: every texel's list length and
+    kept ids exactly, its colour and coverage, and every gradient (all six point arrays, the
+    background and the camera, a sum over all points)."""
+    from oracle import parallel
     sc = scenes.cluster_scene(2)
     cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
     P = oracle.num_pixels(cam["W"], cam["H"], nl)
     bg, G, Ga = _inputs(P, D, 60)
     got = _gpu(sc, gpu, bg, G, Ga)
-    f = oracle.forward_ex(sc["points"], cam, nl, background=bg.astype(np.float64))
+    f = parallel.forward(sc["points"], cam, nl, background=bg.astype(np.float64))
+    assert_lists(got["counts"], got["ids"], f["counts"], f["ids"], "full size")
     assert np.abs(got["coverage"] - f["alpha"]).max() <= ALPHA_ATOL
     assert_pyramid(got["pyr"], f["pyr"], "full size")
-    b = oracle.backward_ex(sc["points"], cam, nl, G.astype(np.float64),
-                           background=bg.astype(np.float64), grad_alpha=Ga.astype(np.float64))
+    b = parallel.backward(sc["points"], cam, nl, G.astype(np.float64),
+                          background=bg.astype(np.float64), grad_alpha=Ga.astype(np.float64))
+    for k in PARAMS:
+        grad_close(got[k], b[GRAD_KEY[k]].reshape(got[k].shape), k)
     grad_close(got["gcam"][0], b["gcam"], "gcam", rtol_norm=1e-4, rtol=1e-2, atol_rel=1e-4)
     grad_close(got["gbg"], b["gbg"], "gbg")
