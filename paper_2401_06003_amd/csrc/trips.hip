@@ -388,8 +388,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const flo
 // column scan, whose workgroups cover the same chunks), then two short passes.  A tile
 // of at most FINE_E entries is listed in fine_work; every other tile is listed in coarse_bins
 // and cut into ceil(total / item_e) work items; tiles with more than one item are listed in
-// multi_bins (their partial lists are merged).  bin_start and item_start are the exclusive
-// scans of entries and items.
+// multi_bins (their partial lists are merged), with the first of their items' consecutive
+// partial-list slots NB words further on.  bin_start and item_start are the exclusive scans
+// of entries and items.
 constexpr uint32_t CHUNK = 64;
 constexpr int CSUM = 4 + NBUCKET;  // per chunk: entries, items, multi tiles, fine tiles, classes
 
@@ -656,7 +657,10 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
   if (b < NB) {
     bin_start[b] = oe;
     item_start[b] = oi;
-    if (c.multi) multi_bins[om] = b;
+    if (c.multi) {  // the tile and the first of its items' partial-list slots
+      multi_bins[om] = b;
+      multi_bins[NB + om] = oi - (b - om - of);
+    }
     if (c.fine) fine_work[of] = make_uint4(b, oe, oe + c.e, 0u);
     else coarse_bins[b - of] = b;  // tiles before b that are not fine
   }
@@ -672,12 +676,15 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
     s_base[t] = info[INFO_BUCKET + t] + atomicAdd(&info[INFO_BUCKET + NBUCKET + t], s_cnt[t]);
   __syncthreads();
   if (!c.it) return;
+  // items of multi-item tiles carry their partial-list slot: the items of such tiles before
+  // this one (oi counts one item for each of the b - om - of single-item tiles before it)
   const uint32_t multi = c.it > 1 ? 0x80000000u : 0u;
+  const uint32_t pslot = multi ? oi - (b - om - of) : 0u;
   for (uint32_t k = 0; k < nfull; ++k) {
     const uint32_t e0 = oe + k * item_e;
-    work[s_base[0] + rf + k] = make_uint4(b, e0, e0 + item_e, (oi + k) | multi);
+    work[s_base[0] + rf + k] = make_uint4(b, e0, e0 + item_e, (pslot + k) | multi);
   }
-  work[s_base[q] + rl] = make_uint4(b, elast, oe + c.e, (oi + c.it - 1) | multi);
+  work[s_base[q] + rl] = make_uint4(b, elast, oe + c.e, (pslot + c.it - 1) | multi);
 }
 
 // scatter: the count pass again, with LDS ranks; entry -> bin_start + H (column prefix) + rank.
@@ -1250,9 +1257,11 @@ __global__ __launch_bounds__(256) void k_fwd_merge(
   const int lane = threadIdx.x & 63;
   const int slice = threadIdx.x >> 6;
   for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-    const uint32_t b = multi_bins[u / (TP / 64)];
+    const uint32_t mb = u / (TP / 64);
+    const uint32_t b = multi_bins[mb];
     const int t = int(u % (TP / 64)) * 64 + lane;  // texel
-    const uint32_t i0 = item_start[b], i1 = item_start[b + 1];
+    // the tile's items' partial lists: consecutive slots from multi_bins[NB + mb]
+    const uint32_t i0 = multi_bins[P.NB + mb], i1 = i0 + (item_start[b + 1] - item_start[b]);
     uint64_t kk[KEEP];
     float kg[KEEP];
 #pragma unroll
@@ -2464,7 +2473,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.s_info = take(64 * 4);
   lay.s_bin_start = take((NB + 1) * 4);
   lay.s_item_start = take((NB + 1) * 4);
-  lay.s_multi = take(NB * 4);
+  lay.s_multi = take(2 * NB * 4);
   lay.s_fine = take(NB * sizeof(uint4));
   lay.s_coarse = take(NB * 4);
   // texel tables: their offsets depend only on the cameras and config (export reads them)
@@ -2489,9 +2498,12 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.w_tot = take(NB * 4);
   lay.w_csum = take(((NB + CHUNK - 1) / CHUNK) * CSUM * 4);
   lay.w_coff = take(((NB + CHUNK - 1) / CHUNK) * 4 * 4);
-  lay.w_pcnt = take(size_t(lay.icap) * TP * 4);
-  lay.w_pkey = take(size_t(lay.icap) * TP * KEEP * 8);
-  lay.w_pgam = take(size_t(lay.icap) * TP * KEEP * 4);
+  // partial lists of the items of multi-item tiles only: such a tile has e > item_e entries
+  // and ceil(e / item_e) < 2 e / item_e items, so they number fewer than 2 ecap / item_e
+  const uint64_t pcap = std::min<uint64_t>(lay.icap, 2 * lay.ecap / item_e + 1);
+  lay.w_pcnt = take(size_t(pcap) * TP * 4);
+  lay.w_pkey = take(size_t(pcap) * TP * KEEP * 8);
+  lay.w_pgam = take(size_t(pcap) * TP * KEEP * 4);
   const size_t fwd_end = o;
   // backward scratch reuses the same bytes
   o = scratch;
