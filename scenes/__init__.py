@@ -224,3 +224,34 @@ def random_small(seed, n=64, W=32, H=24, nlayers=4, D=4, s_lo=0.3, s_hi=12.0, de
     desc = rng.uniform(0.0, 1.0, (n, D))
     xyz = np.stack([x, y, z], axis=1)
     return {"points": _points(xyz, sw, alpha, desc), "cams": [cam], "nlayers": nlayers, "D": D}
+
+
+def decoder_weights(seed, nlayers, D=4, out_dim=3, features=32):
+    """Seeded weights of the reconstruction network (trained weights are not available):
+    per layer a 3x3 kernel [3, 3, C_in, 2 features] with C_in = D for the coarsest layer and
+    D + features otherwise, drawn N(0, 1 / (9 C_in)) and rounded to binary16 (the kernels are
+    given in that format), and a bias [2 features] N(0, 0.1^2) float32; the output layer
+    [features, out_dim] N(0, 1 / features) and its bias, float32."""
+    rng = np.random.default_rng(seed)
+    w, b = [], []
+    for L in range(nlayers):
+        cin = D if L == nlayers - 1 else D + features
+        k = rng.standard_normal((3, 3, cin, 2 * features)) / math.sqrt(9.0 * cin)
+        w.append(k.astype(np.float16))
+        b.append((0.1 * rng.standard_normal(2 * features)).astype(np.float32))
+    wo = (rng.standard_normal((features, out_dim)) / math.sqrt(features)).astype(np.float32)
+    bo = (0.1 * rng.standard_normal(out_dim)).astype(np.float32)
+    return {"w": w, "b": b, "wo": wo, "bo": bo}
+
+
+def feature_pyramid(seed, W, H, nlayers, D=4, empty_frac=0.2):
+    """A seeded stand-in for a rendered pyramid: per layer [H_L, W_L, D] float32 with
+    W_L = ceil(W / 2^L), values U[0, 1], and a fraction of texels zero (holes)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for L in range(nlayers):
+        w_l, h_l = -(-W // (1 << L)), -(-H // (1 << L))
+        a = rng.uniform(0.0, 1.0, (h_l, w_l, D)).astype(np.float32)
+        a[rng.random((h_l, w_l)) < empty_frac] = 0.0
+        out.append(a)
+    return out
