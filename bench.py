@@ -1,7 +1,7 @@
 """Benchmark: splatted points per second for forward+backward trilinear point splatting.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                [--no-coarser] [--no-optim] [--no-8m] [--opt-iters N]
+                [--no-coarser] [--no-optim] [--no-8m] [--no-decoder] [--opt-iters N]
 
 Headline workload (one step = the whole hot path once): 2M points drawn from 64 anisotropic
 Gaussian clusters plus 30% on planar patches, one 1920x1080 pinhole view, 8 pyramid layers,
@@ -16,7 +16,8 @@ reported: per-kernel durations (eager steps with HIP events around every launch,
 stream); the roofline of the dominant kernel in the method's own byte units (per fragment,
 kept fragment, texel and point) beside the implementation's byte model; the whole step's
 fraction of HBM peak; a plain device copy's bandwidth; the forward alone at the same size;
-the 4096-point 256x256 forward latency; the same workload with coarser-layer inclusion; the
+the 4096-point 256x256 forward latency; the reconstruction network (Sec. 3.3) on the rendered
+pyramid, with its matrix-core roofline; the same workload with coarser-layer inclusion; the
 batched multi-view form (16 views of mixed resolution over 4M points, autotuned launch shape)
 against 16 single-view launch sequences; 8M points at 1080p; the optimisation loop (8M
 points, 8 views of 2560x1440, D = 8, 100 iterations of fwd + bwd + Adam against targets the
@@ -553,6 +554,65 @@ def run_optimisation(torch, tp, scenes, iters, warmup, dev):
             "oracle_targets_s": oracle_s, "oracle_cores": workers}
 
 
+def decoder_flops(dims, D, out_dim, features=32):
+    """Multiply-adds x 2 of the network on layer sizes `dims` [(W_L, H_L)], finest first: per
+    texel of layer L a 3x3 convolution of C_in(L) channels (D for the coarsest layer, D + 32
+    otherwise) to 64 outputs, and the 1x1 output layer on layer 0."""
+    nl = len(dims)
+    f = 0
+    for L, (w, h) in enumerate(dims):
+        cin = D if L == nl - 1 else D + features
+        f += 2 * w * h * 9 * cin * 2 * features
+    w0, h0 = dims[0]
+    return f + 2 * w0 * h0 * features * out_dim
+
+
+def run_decoder(torch, tp, scenes, pyr, cam, nl, D, steps, warmup, dev, cpu=True):
+    """The reconstruction network (Sec. 3.3) on the headline view's rendered pyramid
+    (1920x1080, 8 layers, D = 4, 3 output channels, seeded binary16 weights): whole-network
+    time, the finest block alone, and the matrix-core roofline of the finest block (its
+    algorithmic multiply-adds over its time, against the binary16 dense peak); the oracle's
+    double-precision network on the host beside it."""
+    import numpy as np
+    W, H = cam["W"], cam["H"]
+    wt = scenes.decoder_weights(61, nl, D)
+    d = tp.Decoder(W, H, nl, D, wt, device=dev)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        d.forward(pyr, img)
+    ms = timed(torch, lambda: d.forward(pyr, img), steps)
+    # the finest block alone (block 1's output as its input, the output layer applied)
+    W1, H1 = d.dims[1]
+    h1 = torch.zeros((H1, W1, 32), dtype=torch.float16, device=dev)
+    f0 = pyr[:W * H * D].view(H, W, D)
+    ms0 = timed(torch, lambda: d.block(0, f0, h1, final=True), steps)
+    fl = decoder_flops(d.dims, D, 3)
+    fl0 = 2 * W * H * (9 * (D + 32) * 64 + 32 * 3)
+    peak = 2500.0  # TFLOP/s, binary16 dense matrix cores
+    out = {"workload": "decoder_1920x1080_8layers_d4_out3_fp16", "ms": ms,
+           "frames_per_s": 1e3 / ms, "flops": fl, "tflops": fl / (ms / 1e3) / 1e12,
+           "layer0_ms": ms0,
+           "roofline": {"bound": "mfma", "kernel": "dec_block (layer 0)",
+                        "achieved": fl0 / (ms0 / 1e3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                        "frac": fl0 / (ms0 / 1e3) / 1e12 / peak, "flops_per_launch": fl0}}
+    if cpu:
+        from oracle import decoder as dec
+        host = pyr.cpu().numpy().astype(np.float64)
+        layers, o = [], 0
+        for (w, h) in d.dims:
+            layers.append(host[o:o + w * h * D].reshape(h, w, D))
+            o += w * h * D
+        t0 = time.perf_counter()
+        dec.decode(layers, wt, fp16=True)
+        sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / sec, "unit": "frames/s", "kind": "oracle",
+                               "cores": torch.get_num_threads(),
+                               "sample": "one 1920x1080 frame, 8 layers, double precision "
+                                         "numpy (its matrix products on %d threads), %.1f s" %
+                                         (torch.get_num_threads(), sec)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -563,6 +623,7 @@ def main():
     ap.add_argument("--no-coarser", action="store_true")
     ap.add_argument("--no-optim", action="store_true")
     ap.add_argument("--no-8m", action="store_true")
+    ap.add_argument("--no-decoder", action="store_true")
     ap.add_argument("--opt-iters", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference for "
@@ -675,6 +736,11 @@ def main():
                                            None if args.no_cpu_baseline else sc)
     log("4096 points at 256x256")
     out["small"] = run_small_latency(torch, tp, scenes, args.steps, dev)
+    if not args.no_decoder:
+        log("reconstruction network on the rendered pyramid")
+        r.forward(*pargs, out=pyr)
+        out["decoder"] = run_decoder(torch, tp, scenes, pyr, cam, nl, D, args.steps,
+                                     args.warmup, dev, not args.no_cpu_baseline)
     if not args.no_coarser:
         log("coarser-layer inclusion on the same workload")
         out["coarser"] = run_coarser(torch, tp, sc, pargs, G, args.steps, args.warmup, dev, ms)

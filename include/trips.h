@@ -122,15 +122,22 @@ typedef struct {
   float* grad_camera;
 } trips_extras;
 
-/* Host only.  Layer sizes of one view: dims_host[2L] = W_L, dims_host[2L+1] = H_L, and
-   offsets_host[L] = first texel of layer L in the concatenated pyramid of that view,
-   offsets_host[num_layers] = total texels.  Either output may be NULL. */
+/* Host only.  Layer sizes of one view's image pyramid (Sec. 3.1: layer L has texels of
+   2^L pixels; for sizes not divisible by 2^L the layer is rounded up, W_L = ceil(W / 2^L)):
+   dims_host[2L] = W_L, dims_host[2L+1] = H_L, and offsets_host[L] = first texel of layer L
+   in the concatenated pyramid of that view, offsets_host[num_layers] = total texels.
+   Either output may be NULL.  Errors: INVALID_ARG for a null struct, a layer count outside
+   1..TRIPS_MAX_LAYERS or a view size outside 1..65536. */
 trips_status trips_layer_layout(const trips_camera* cam_host, const trips_config* cfg_host,
                                 int32_t* dims_host, int64_t* offsets_host);
 
 /* Host only.  Bytes of the `workspace` (scratch, any call) and `saved` (written by the
    forward pass, read by backward and export) buffers for `views` cameras and n points.
-   Both buffers must be 256-byte aligned. */
+   `saved` holds what Sec. 3.6 keeps from the forward pass for the backward pass: the
+   sorted per-texel lists (here clamped to the 16 kept fragments, Sec. 3.2) and their
+   lengths, plus the tile entries; every capacity is a worst case, so no call needs to
+   read a count back to the host.  Both buffers must be 256-byte aligned.  Errors as
+   trips_forward's argument checks (INVALID_ARG, UNSUPPORTED, CAPACITY). */
 trips_status trips_buffer_sizes(const trips_config* cfg_host, const trips_camera* cams_host,
                                 int32_t views, int64_t n, const trips_tuning* tuning_host,
                                 size_t* workspace_bytes, size_t* saved_bytes);
@@ -146,7 +153,10 @@ trips_status trips_forward(const trips_config* cfg_host, const trips_points* pts
                            size_t saved_bytes, void* workspace, size_t workspace_bytes,
                            const trips_extras* extras_host, hipStream_t stream);
 
-/* Backward of sum(grad_pyramid * pyramid) for the forward call that filled `saved`
+/* The pipeline is differentiable end to end (Sec. 1 and 3: point positions, sizes,
+   descriptors and opacities are optimised by gradient descent); this is the renderer's
+   part of that, the adjoint of Eq. 6-7 through Eq. 2-5.
+   Backward of sum(grad_pyramid * pyramid) for the forward call that filled `saved`
    (same points, cameras, config and tuning).  grad_pyramid has the pyramid layout.
    All six gradient outputs are device float32 arrays ([n], desc [n][D]) and are
    OVERWRITTEN (culled points get 0).  The per-texel blend state is recomputed from the
@@ -243,6 +253,71 @@ trips_status trips_plan_create(const trips_config* cfg_host, const trips_points*
 /* which: 1 = forward, 2 = backward, 3 = both (in that order). */
 trips_status trips_plan_launch(trips_plan* plan, int32_t which, hipStream_t stream);
 void trips_plan_destroy(trips_plan* plan);
+
+/* ---------------------------------------------------------------------------------
+   Reconstruction network (Sec. 3.3, Fig. conv): the feature pyramid of one view becomes one
+   full-resolution image.  One block per layer, coarsest first; block L reads its layer's D
+   feature channels and, below the coarsest layer, the bilinear doubling of block L+1's
+   output (texel k of layer L+1 centred where texels 2k and 2k+1 of layer L meet, edge
+   texels repeated, cropped to layer L); it is one gated 3x3 convolution (zero padding,
+   2 x TRIPS_DEC_FEATURES outputs: ELU of the first half times the logistic sigmoid of the
+   second half) plus, below the coarsest layer, the doubled input features (the
+   self-bypass).  The finest block's features go through a 1x1 convolution to out_dim
+   channels.  Binary16 operands, float32 accumulation: the layer features, the doubled
+   features and every block output are rounded to binary16 (nearest even) where they are
+   stored. */
+#define TRIPS_DEC_FEATURES 32
+
+typedef struct {
+  int32_t num_layers;    /* n, 1..TRIPS_MAX_LAYERS (the pyramid's layers) */
+  int32_t desc_dim;      /* D, the pyramid's channels: 4 or 8 */
+  int32_t out_dim;       /* output channels, 1..8 (3 for RGB) */
+  int32_t width, height; /* layer 0 resolution; layer L is ceil(width/2^L) x ceil(height/2^L) */
+} trips_decoder_config;
+
+/* Network weights, device pointers.  kernel[L]: binary16 bit patterns, [3][3][C_in][64]
+   row-major (tap row, tap column, input channel, output), C_in = D for the coarsest layer and
+   D + 32 otherwise (the layer's channels first, then the doubled features); outputs 0..31
+   are the feature half, 32..63 the gate half.  bias[L]: float32 [64].  out_weight: float32
+   [32][out_dim]; out_bias: float32 [out_dim]. */
+typedef struct {
+  const uint16_t* kernel[TRIPS_MAX_LAYERS];
+  const float* bias[TRIPS_MAX_LAYERS];
+  const float* out_weight;
+  const float* out_bias;
+} trips_decoder_weights;
+
+/* Host only.  Bytes of the packed weights (trips_decoder_pack) and of the workspace of
+   trips_decoder_forward (the block outputs of layers 1..n-1, binary16); both buffers
+   256-byte aligned. */
+trips_status trips_decoder_sizes(const trips_decoder_config* cfg_host, size_t* packed_bytes,
+                                 size_t* workspace_bytes);
+
+/* Rewrites the weights into the matrix-core operand order the convolution reads (once per
+   set of weights; enqueued on `stream`).  `packed` is caller-owned device memory. */
+trips_status trips_decoder_pack(const trips_decoder_config* cfg_host,
+                                const trips_decoder_weights* weights_host, void* packed,
+                                size_t packed_bytes, hipStream_t stream);
+
+/* The whole network.  pyramid: float32, layers in order, each row-major [H_L][W_L][D] (the
+   layout trips_forward writes for one view), 16-byte aligned.  image: float32
+   [height][width][out_dim], overwritten. */
+trips_status trips_decoder_forward(const trips_decoder_config* cfg_host, const void* packed,
+                                   size_t packed_bytes, const float* pyramid, float* image,
+                                   void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One block, for tests and callers that schedule the layers themselves.  features: float32
+   [H_L][W_L][D] of layer `layer`; coarse: binary16 [H_{L+1}][W_{L+1}][32], block L+1's
+   output (ignored, may be NULL, for the coarsest layer).  Exactly one of `out` (binary16
+   [H_L][W_L][32], the block's output) and `image` (float32 [H_L][W_L][out_dim], the output
+   layer applied to the block's output) is non-NULL.  16-byte aligned. */
+trips_status trips_decoder_block(const trips_decoder_config* cfg_host, const void* packed,
+                                 size_t packed_bytes, int32_t layer, const float* features,
+                                 const uint16_t* coarse, uint16_t* out, float* image,
+                                 hipStream_t stream);
+
+/* HIP error code of the last decoder call that returned TRIPS_ERR_HIP. */
+int32_t trips_decoder_last_hip_error(void);
 
 #ifdef __cplusplus
 }

@@ -471,3 +471,126 @@ class TripsSplat(torch.autograd.Function):
 def render(x, y, z, sw, alpha, desc, renderer):
     """Flat pyramid of `renderer`'s views; differentiable in all six point arrays."""
     return TripsSplat.apply(x, y, z, sw, alpha, desc, renderer)
+
+
+# ---------------------------------------------------------------------------------------
+# Reconstruction network (Sec. 3.3): trips_decoder_* in include/trips.h.
+
+DEC_FEATURES = 32
+
+
+class DecoderConfig(ctypes.Structure):
+    _fields_ = [("num_layers", c_int32), ("desc_dim", c_int32), ("out_dim", c_int32),
+                ("width", c_int32), ("height", c_int32)]
+
+
+class DecoderWeights(ctypes.Structure):
+    _fields_ = [("kernel", c_void_p * 12), ("bias", c_void_p * 12), ("out_weight", c_void_p),
+                ("out_bias", c_void_p)]
+
+
+def _declib():
+    L = lib()
+    if not getattr(L, "_dec_ready", False):
+        P = ctypes.POINTER
+        L.trips_decoder_sizes.argtypes = [P(DecoderConfig), P(c_size_t), P(c_size_t)]
+        L.trips_decoder_pack.argtypes = [P(DecoderConfig), P(DecoderWeights), c_void_p, c_size_t,
+                                         c_void_p]
+        L.trips_decoder_forward.argtypes = [P(DecoderConfig), c_void_p, c_size_t, c_void_p,
+                                            c_void_p, c_void_p, c_size_t, c_void_p]
+        L.trips_decoder_block.argtypes = [P(DecoderConfig), c_void_p, c_size_t, c_int32,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        for name in ("trips_decoder_sizes", "trips_decoder_pack", "trips_decoder_forward",
+                     "trips_decoder_block", "trips_decoder_last_hip_error"):
+            getattr(L, name).restype = c_int32
+        L._dec_ready = True
+    return L
+
+
+def _dcheck(status, what):
+    if status != 0:
+        if status == -4:
+            what = "%s (hip error %d)" % (what, _declib().trips_decoder_last_hip_error())
+        raise TripsError(status, what)
+
+
+class Decoder:
+    """The reconstruction network of one view size: packs the weights once (device memory
+    from torch) and runs the whole network or single blocks.
+
+    weights: {"w": [L] binary16 kernels [3, 3, C_in, 64], "b": [L] float32 [64],
+    "wo": float32 [32, out_dim], "bo": float32 [out_dim]} (numpy or torch)."""
+
+    def __init__(self, width, height, num_layers, desc_dim, weights, device="cuda"):
+        self.device = torch.device(device)
+        out_dim = int(weights["wo"].shape[1])
+        self.cfg = DecoderConfig(int(num_layers), int(desc_dim), out_dim, int(width), int(height))
+        self.nl, self.D, self.out_dim = int(num_layers), int(desc_dim), out_dim
+        pb, wb = c_size_t(), c_size_t()
+        _dcheck(_declib().trips_decoder_sizes(ctypes.byref(self.cfg), ctypes.byref(pb),
+                                              ctypes.byref(wb)), "trips_decoder_sizes")
+        self.packed_bytes, self.ws_bytes = pb.value, wb.value
+        self.packed = _aligned_bytes(self.packed_bytes, self.device)
+        self.workspace = _aligned_bytes(self.ws_bytes, self.device)
+        self.dims = [(-(-int(width) // (1 << L)), -(-int(height) // (1 << L)))
+                     for L in range(self.nl)]
+
+        def dev(a, dtype):
+            t = torch.as_tensor(a)
+            if dtype == torch.float16:
+                t = t.to(torch.float16).view(torch.int16)
+            else:
+                t = t.to(dtype)
+            return t.contiguous().to(self.device)
+
+        self._w = [dev(k, torch.float16) for k in weights["w"]]
+        self._b = [dev(b, torch.float32) for b in weights["b"]]
+        self._wo = dev(weights["wo"], torch.float32)
+        self._bo = dev(weights["bo"], torch.float32)
+        for L, k in enumerate(self._w):
+            cin = self.D if L == self.nl - 1 else self.D + DEC_FEATURES
+            if tuple(k.shape) != (3, 3, cin, 2 * DEC_FEATURES):
+                raise ValueError("layer %d kernel must be [3, 3, %d, 64]" % (L, cin))
+        ws = DecoderWeights()
+        for L in range(self.nl):
+            ws.kernel[L] = self._w[L].data_ptr()
+            ws.bias[L] = self._b[L].data_ptr()
+        ws.out_weight, ws.out_bias = self._wo.data_ptr(), self._bo.data_ptr()
+        _dcheck(_declib().trips_decoder_pack(ctypes.byref(self.cfg), ctypes.byref(ws),
+                                             _ptr(self.packed), self.packed_bytes, _stream()),
+                "trips_decoder_pack")
+
+    def forward(self, pyramid, image=None):
+        """pyramid: flat float32 (layers in order, [H_L][W_L][D]) -> image [H, W, out_dim]."""
+        W, H = self.dims[0]
+        if pyramid.dtype != torch.float32 or not pyramid.is_contiguous():
+            raise ValueError("pyramid must be contiguous float32")
+        if pyramid.numel() != sum(w * h for w, h in self.dims) * self.D:
+            raise ValueError("pyramid size does not match the decoder")
+        if image is None:
+            image = torch.empty((H, W, self.out_dim), dtype=torch.float32, device=self.device)
+        _dcheck(_declib().trips_decoder_forward(ctypes.byref(self.cfg), _ptr(self.packed),
+                                                self.packed_bytes, _ptr(pyramid), _ptr(image),
+                                                _ptr(self.workspace), self.ws_bytes, _stream()),
+                "trips_decoder_forward")
+        return image
+
+    def block(self, layer, features, coarse=None, final=False):
+        """One block: features float32 [H_L, W_L, D]; coarse binary16 [H_L+1, W_L+1, 32] (None
+        for the coarsest layer).  Returns the block output (float16 [H_L, W_L, 32]) or, with
+        final=True, the output layer applied to it (float32 [H_L, W_L, out_dim])."""
+        W, H = self.dims[layer]
+        features = features.contiguous()
+        if coarse is not None:
+            coarse = coarse.contiguous()
+        if final:
+            out = torch.empty((H, W, self.out_dim), dtype=torch.float32, device=self.device)
+            args = (c_void_p(0), _ptr(out))
+        else:
+            out = torch.empty((H, W, DEC_FEATURES), dtype=torch.float16, device=self.device)
+            args = (_ptr(out), c_void_p(0))
+        _dcheck(_declib().trips_decoder_block(ctypes.byref(self.cfg), _ptr(self.packed),
+                                              self.packed_bytes, int(layer), _ptr(features),
+                                              _ptr(coarse), *args, _stream()),
+                "trips_decoder_block")
+        return out

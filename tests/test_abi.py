@@ -169,3 +169,62 @@ def test_view_with_too_many_tiles_is_unsupported():
     pts = tp.Points(fake, fake, fake, fake, fake, fake, 1000)
     assert L.trips_forward(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None, fake, fake,
                            1 << 40, fake, 1 << 40, None, None) == -5
+
+
+def _dec_cfg(tp, nl=4, D=4, out_dim=3, W=64, H=48):
+    return tp.DecoderConfig(nl, D, out_dim, W, H)
+
+
+def test_decoder_sizes():
+    tp, L = _lib()
+    L = tp._declib()
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.trips_decoder_sizes(ctypes.byref(_dec_cfg(tp, 8, 4, 3, 1920, 1080)),
+                                 ctypes.byref(pb), ctypes.byref(wb)) == 0
+    # block outputs of layers 1..7 in binary16: 32 channels of every texel below layer 0
+    below = sum((-(-1920 // (1 << l))) * (-(-1080 // (1 << l))) for l in range(1, 8))
+    assert below * 64 <= wb.value <= below * 64 + 7 * 256
+    # packed kernels: (9 + 2) steps x 4 KB per layer but the coarsest (2 steps), plus biases
+    assert pb.value >= 7 * 11 * 4096 + 2 * 4096 + 8 * 256
+
+
+@pytest.mark.parametrize("cfg,code", [
+    ((0, 4, 3, 64, 48), -1),    # no layers
+    ((13, 4, 3, 64, 48), -1),   # too many layers
+    ((4, 6, 3, 64, 48), -5),    # channel count not built
+    ((4, 4, 0, 64, 48), -1),    # no output channels
+    ((4, 4, 9, 64, 48), -1),    # too many output channels
+    ((4, 4, 3, 0, 48), -1),     # empty view
+])
+def test_decoder_invalid_config(cfg, code):
+    tp, L = _lib()
+    L = tp._declib()
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.trips_decoder_sizes(ctypes.byref(tp.DecoderConfig(*cfg)), ctypes.byref(pb),
+                                 ctypes.byref(wb)) == code
+
+
+def test_decoder_calls_validate_before_launching():
+    """Bad pointers, sizes and layer indices are refused on the host (nothing is launched,
+    so no device is needed)."""
+    tp, L = _lib()
+    L = tp._declib()
+    cfg = _dec_cfg(tp)
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    L.trips_decoder_sizes(ctypes.byref(cfg), ctypes.byref(pb), ctypes.byref(wb))
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: validation fails first
+    null = ctypes.c_void_p(0)
+    assert L.trips_decoder_pack(ctypes.byref(cfg), ctypes.byref(tp.DecoderWeights()), fake,
+                                pb.value, null) == -1  # missing kernels
+    assert L.trips_decoder_forward(ctypes.byref(cfg), fake, pb.value - 1, fake, fake, fake,
+                                   wb.value, null) == -2  # packed buffer too small
+    assert L.trips_decoder_forward(ctypes.byref(cfg), fake, pb.value, fake, fake, fake,
+                                   wb.value - 1, null) == -2  # workspace too small
+    assert L.trips_decoder_forward(ctypes.byref(cfg), fake, pb.value, null, fake, fake,
+                                   wb.value, null) == -1  # no pyramid
+    assert L.trips_decoder_block(ctypes.byref(cfg), fake, pb.value, 4, fake, fake, fake, null,
+                                 null) == -1  # layer out of range
+    assert L.trips_decoder_block(ctypes.byref(cfg), fake, pb.value, 1, fake, null, fake, null,
+                                 null) == -1  # a layer below the coarsest needs its input
+    assert L.trips_decoder_block(ctypes.byref(cfg), fake, pb.value, 3, fake, null, fake, fake,
+                                 null) == -1  # both outputs given
