@@ -153,6 +153,25 @@ trips_status trips_forward(const trips_config* cfg_host, const trips_points* pts
                            size_t saved_bytes, void* workspace, size_t workspace_bytes,
                            const trips_extras* extras_host, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): trips_forward with the same arguments
+   minus the workspace.  The forward scratch (the part of trips_buffer_sizes' workspace a
+   forward call uses) is taken from a device array inside the library of
+   TRIPS_STATIC_SCRATCH_MB MiB, one per GPU the library runs on, held until the process
+   ends; problems whose forward scratch is larger return TRIPS_ERR_WORKSPACE (the headline
+   view, 2M points at 1920x1080 with 8 layers, needs about 220 MB).  No allocation of any
+   kind is made.  Every call on one GPU uses that GPU's one array: calls that overlap on a
+   device (different streams, or host threads without ordering) race and give undefined
+   results; calls ordered on one stream are safe.  `saved` is the caller's, as for
+   trips_forward, and trips_backward / trips_export_fragments read it as usual (the
+   backward still takes a caller workspace). */
+#define TRIPS_STATIC_SCRATCH_MB 256
+trips_status trips_forward_noalloc(const trips_config* cfg_host, const trips_points* pts_host,
+                                   const trips_camera* cams_host, int32_t views,
+                                   const trips_tuning* tuning_host, float* pyramid_out,
+                                   void* saved, size_t saved_bytes,
+                                   const trips_extras* extras_host, hipStream_t stream);
+
 /* The pipeline is differentiable end to end (Sec. 1 and 3: point positions, sizes,
    descriptors and opacities are optimised by gradient descent); this is the renderer's
    part of that, the adjoint of Eq. 6-7 through Eq. 2-5.

@@ -70,6 +70,9 @@ def lib():
                                          P(c_size_t), P(c_size_t)]
         L.trips_forward.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_void_p,
                                     c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]
+        L.trips_forward_noalloc.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning),
+                                            c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
+        L.trips_forward_noalloc.restype = c_int32
         L.trips_backward.argtypes = [P(Config), P(Points), P(Camera), c_int32, P(Tuning), c_void_p,
                                      c_void_p, c_size_t, c_void_p, c_size_t] + [c_void_p] * 8
         L.trips_export_fragments.argtypes = [P(Config), P(Camera), c_int32, P(Tuning), c_void_p,
@@ -258,6 +261,25 @@ class Renderer:
                                    self.saved_bytes, _ptr(self.workspace), self.ws_bytes, ext,
                                    _stream()),
                "trips_forward")
+        return out
+
+    def forward_noalloc(self, x, y, z, sw, alpha, desc, out=None, background=None,
+                        alpha_out=None):
+        """forward() through trips_forward_noalloc: the forward scratch comes from the
+        library's static per-GPU array instead of this renderer's workspace (the `out`
+        pyramid and the `saved` buffer are still this renderer's)."""
+        pts = self._points(x, y, z, sw, alpha, desc)
+        if out is None:
+            out = torch.empty(self.pyramid_numel(), dtype=torch.float32, device=self.device)
+        self._texel_array(background, self.D, "background")
+        self._texel_array(alpha_out, 1, "alpha_out")
+        keep, ext = _extras(background=background, alpha_out=alpha_out)
+        self._saved_state.generation += 1
+        self._saved_state.owner = self
+        _check(lib().trips_forward_noalloc(ctypes.byref(self.cfg), ctypes.byref(pts), self.cams,
+                                           self.V, ctypes.byref(self.tune), _ptr(out),
+                                           _ptr(self.saved), self.saved_bytes, ext, _stream()),
+               "trips_forward_noalloc")
         return out
 
     def backward(self, x, y, z, sw, alpha, desc, grad_pyramid, outs=None, background=None,

@@ -2387,6 +2387,7 @@ struct Layout {
   // workspace
   size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, w_itot, w_iup,
       ws_bytes;
+  size_t ws_fwd_bytes;  // the part of the workspace a forward call uses
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -2513,6 +2514,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.w_itot = take(inc * NB * TP * KEEP * size_t(1 + P.D) * 4);
   lay.w_iup = take(inc * NB * TP * KEEP * size_t(1 + P.D) * 4);
   lay.ws_bytes = std::max(fwd_end, o);
+  lay.ws_fwd_bytes = fwd_end;
   return TRIPS_OK;
 }
 
@@ -2547,6 +2549,30 @@ trips_status check_points(const trips_points* pts, const Layout& lay) {
   if (pts->n > 0 && (!pts->x || !pts->y || !pts->z || !pts->size_w || !pts->opacity || !pts->desc))
     return TRIPS_ERR_INVALID_ARG;
   if (pts->n > 0 && !aligned16(pts->desc)) return TRIPS_ERR_INVALID_ARG;
+  return TRIPS_OK;
+}
+
+// Forward scratch for callers that cannot allocate device memory (trips_forward_noalloc):
+// a device array of the library, one copy per GPU, alive until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): each device's address is looked up once, with that device current, and kept.
+constexpr size_t kStaticScratchBytes = size_t(TRIPS_STATIC_SCRATCH_MB) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_make;
+void* g_scratch_ptr[64];
+
+trips_status static_scratch(void*& out) {
+  int dev = 0;
+  TRIPS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return TRIPS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_make);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    TRIPS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || !aligned(p)) return TRIPS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  out = g_scratch_ptr[dev];
   return TRIPS_OK;
 }
 
@@ -2929,6 +2955,29 @@ trips_status trips_forward(const trips_config* cfg, const trips_points* pts,
   if (!pyr || !aligned16(pyr)) return TRIPS_ERR_INVALID_ARG;
   Extras X;
   if ((s = take_extras(extras, true, false, X)) != TRIPS_OK) return s;
+  char* sv = static_cast<char*>(saved);
+  char* w = static_cast<char*>(ws);
+  return cfg->desc_dim == 4 ? launch_forward<4>(lay, *pts, pyr, sv, w, X, st)
+                            : launch_forward<8>(lay, *pts, pyr, sv, w, X, st);
+}
+
+trips_status trips_forward_noalloc(const trips_config* cfg, const trips_points* pts,
+                                   const trips_camera* cams, int32_t views,
+                                   const trips_tuning* tun, float* pyr, void* saved,
+                                   size_t saved_bytes, const trips_extras* extras,
+                                   hipStream_t st) {
+  Layout lay;
+  trips_status s = make_layout(cfg, cams, views, pts ? pts->n : -1, tun, lay);
+  if (s != TRIPS_OK) return s;
+  if ((s = check_points(pts, lay)) != TRIPS_OK) return s;
+  if ((s = check_buffers(lay, saved, saved_bytes, nullptr, 0, false)) != TRIPS_OK) return s;
+  if (lay.ws_fwd_bytes > kStaticScratchBytes) return TRIPS_ERR_WORKSPACE;
+  if (!pyr || !aligned16(pyr)) return TRIPS_ERR_INVALID_ARG;
+  Extras X;
+  if ((s = take_extras(extras, true, false, X)) != TRIPS_OK) return s;
+  void* ws = nullptr;
+  if ((s = static_scratch(ws)) != TRIPS_OK) return s;
+  // every forward scratch word is written before it is read, so nothing is cleared
   char* sv = static_cast<char*>(saved);
   char* w = static_cast<char*>(ws);
   return cfg->desc_dim == 4 ? launch_forward<4>(lay, *pts, pyr, sv, w, X, st)

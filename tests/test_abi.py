@@ -228,3 +228,29 @@ def test_decoder_calls_validate_before_launching():
                                  null) == -1  # a layer below the coarsest needs its input
     assert L.trips_decoder_block(ctypes.byref(cfg), fake, pb.value, 3, fake, null, fake, fake,
                                  null) == -1  # both outputs given
+
+
+def test_noalloc_forward_limits():
+    """trips_forward_noalloc refuses, on the host and before anything is launched, a problem
+    whose forward scratch exceeds the library's static array (8M points at 1920x1080 need
+    about 0.8 GB), and takes no workspace argument at all."""
+    tp, L = _lib()
+    cams = (tp.Camera * 1)(tp.make_camera(_cam()))
+    cfg = tp.make_config(8, 4)
+    fake = 1 << 20  # aligned, never dereferenced: the size check comes first
+    n = 8_000_000
+    pts = tp.Points(fake, fake, fake, fake, fake, fake, n)
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.trips_buffer_sizes(ctypes.byref(cfg), cams, 1, n, None, ctypes.byref(ws),
+                                ctypes.byref(sv)) == 0
+    st = L.trips_forward_noalloc(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None,
+                                 ctypes.c_void_p(fake), ctypes.c_void_p(fake), sv.value, None,
+                                 ctypes.c_void_p(0))
+    assert st == -2
+    st = L.trips_forward_noalloc(ctypes.byref(cfg), ctypes.byref(pts), cams, 1, None,
+                                 ctypes.c_void_p(fake), ctypes.c_void_p(fake), sv.value - 1,
+                                 None, ctypes.c_void_p(0))
+    assert st == -2  # saved buffer too small
+    st = L.trips_forward_noalloc(ctypes.byref(cfg), None, cams, 1, None, ctypes.c_void_p(fake),
+                                 ctypes.c_void_p(fake), sv.value, None, ctypes.c_void_p(0))
+    assert st == -1
