@@ -1345,9 +1345,36 @@ __global__ __launch_bounds__(256) void k_export(const Params P, const uint32_t* 
   counts[o] = int32_t(n);
   const uint32_t fc = P.coarser ? fcnt[size_t(b) * TP + t] : 0u;
   const uint32_t k = P.coarser ? (fc & 31u) + ((fc >> 5) & 31u) : n;
-  const uint64_t* key = P.coarser ? fkey : kkey;
-  for (int m = 0; m < KEEP; ++m)
-    ids[o * KEEP + m] = uint32_t(m) < k ? int32_t(uint32_t(key[(size_t(b) * KEEP + m) * TP + t])) : -1;
+  if (!P.coarser) {
+    for (int m = 0; m < KEEP; ++m)
+      ids[o * KEEP + m] = uint32_t(m) < k ? int32_t(uint32_t(kkey[(size_t(b) * KEEP + m) * TP + t])) : -1;
+    return;
+  }
+  // layer 0's blended lists are not stored (below a coarser layer): rebuilt from the own list
+  // and the covering layer-1 texel's list (pb, pt) by the origin mask
+  const bool rebuilt = bi.L == 0 && P.nl > 1;
+  uint32_t pb = 0;
+  int pt = 0;
+  if (rebuilt) {
+    const int pi = i >> 1, pj = j >> 1;
+    const int tiles_x1 = (layer_dim(P.view[bi.v].W, 1) + (1 << P.ltw) - 1) >> P.ltw;
+    pb = P.view[bi.v].lbin[1] + uint32_t((pj >> lth) * tiles_x1 + (pi >> P.ltw));
+    pt = ((pj & ((1 << lth) - 1)) << P.ltw) | (pi & ((1 << P.ltw) - 1));
+  }
+  const uint32_t mask = fc >> 16;
+  for (int m = 0; m < KEEP; ++m) {
+    uint64_t key = 0;
+    if (uint32_t(m) < k) {
+      if (rebuilt) {
+        const uint32_t ip = __popc(mask & ((1u << m) - 1u));
+        key = ((mask >> m) & 1u) ? fkey[(size_t(pb) * KEEP + ip) * TP + pt]
+                                 : kkey[(size_t(b) * KEEP + (uint32_t(m) - ip)) * TP + t];
+      } else {
+        key = fkey[(size_t(b) * KEEP + m) * TP + t];
+      }
+    }
+    ids[o * KEEP + m] = uint32_t(m) < k ? int32_t(uint32_t(key)) : -1;
+  }
 }
 
 // g_m = G . tau_m, summed in one fixed order.
@@ -1895,14 +1922,216 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
     }
   }
   }
+  // layer 0's list is rebuilt where it is read (own list, covering list, origin mask): no
+  // finer layer merges it, and it is the largest layer
+  if (L > 0) {
 #pragma unroll
-  for (int m = 0; m < KEEP; ++m)
-    if (uint32_t(m) < k) {
-      fkey[(tb + m) * TP + t] = fk[m];
-      fgam[(tb + m) * TP + t] = fg[m];
-    }
+    for (int m = 0; m < KEEP; ++m)
+      if (uint32_t(m) < k) {
+        fkey[(tb + m) * TP + t] = fk[m];
+        fgam[(tb + m) * TP + t] = fg[m];
+      }
+  }
   fcnt[size_t(b) * TP + t] = io | (ip << 5) | (mask << 16);
   write_texel<D>(C, T, size_t(c.lout[L]) + size_t(j) * WL + i, pyr, bg, alpha);
+}
+
+// incl_fwd_group: layers Lb..Lt in one launch, Lt - Lb at most log2 of the tile's shorter
+// side; one workgroup per tile of layer Lb (grid.y = view).  The texels of layer Lb + k over
+// that tile form a (tw >> k) x (th >> k) block that lies over no other tile of layer Lb, so
+// the workgroup runs the layers itself, coarsest first, with a barrier between layers: each
+// layer merges and blends exactly as k_incl_fwd does, stores its blended lists, and hands
+// them to the next finer layer through LDS.  Layer Lt reads its covering lists (layer Lt + 1,
+// an earlier launch) from memory; the coarsest layer of the pyramid keeps its own lists.
+template <int D>
+__global__ __launch_bounds__(256) void k_incl_fwd_group(
+    const Params P, int Lb, int Lt, const uint32_t* __restrict__ npix,
+    const uint64_t* __restrict__ kkey, const float* __restrict__ kgam, uint64_t* __restrict__ fkey,
+    float* __restrict__ fgam, uint32_t* __restrict__ fcnt, const float* __restrict__ desc,
+    float* __restrict__ pyr, const float* __restrict__ bg, float* __restrict__ alpha) {
+  __shared__ uint64_t s_k[2][KEEP][PT];  // blended lists of a layer's block, for the next layer
+  __shared__ float s_g[2][KEEP][PT];
+  __shared__ uint32_t s_n[2][PT];
+  const int v = blockIdx.y;
+  const ViewP& c = P.view[v];
+  const uint32_t local = blockIdx.x;
+  if (local >= c.lbin[Lb + 1] - c.lbin[Lb]) return;  // uniform per workgroup
+  const int t = threadIdx.x;
+  const int ltw = P.ltw, lth = 8 - P.ltw;
+  const int tiles_x = (layer_dim(c.W, Lb) + (1 << ltw) - 1) >> ltw;
+  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  for (int L = Lt; L >= Lb; --L) {
+    const int k = L - Lb;
+    const int rw = (1 << ltw) >> k, rh = (1 << lth) >> k;  // this layer's block
+    const int cur = k & 1, prev = cur ^ 1;  // LDS lists written here / by layer L + 1
+    if (t < rw * rh) {
+      const int i = tx * rw + t % rw, j = ty * rh + t / rw;
+      const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
+      uint32_t kout = 0;
+      uint64_t fk[KEEP];
+      float fg[KEEP];
+      if (i < WL && j < HL) {
+        uint32_t b;
+        int tt;
+        texel_bin(P, v, L, i, j, b, tt);
+        const size_t tb = size_t(b) * KEEP;
+        const uint32_t ko = min(npix[size_t(b) * TP + tt], uint32_t(KEEP));
+        uint64_t ok[KEEP];
+        float og[KEEP];
+#pragma unroll
+        for (int m = 0; m < KEEP; ++m) {  // every slot read (in bounds), those past ko unused
+          ok[m] = kkey[(tb + m) * TP + tt];
+          og[m] = kgam[(tb + m) * TP + tt];
+        }
+        if (L == P.nl - 1) {  // the coarsest layer keeps its own lists (already blended)
+#pragma unroll
+          for (int m = 0; m < KEEP; ++m) {
+            fk[m] = uint32_t(m) < ko ? ok[m] : KEY_NONE;
+            fg[m] = uint32_t(m) < ko ? og[m] : 0.0f;
+            if (uint32_t(m) < ko) {
+              fkey[(tb + m) * TP + tt] = ok[m];
+              fgam[(tb + m) * TP + tt] = og[m];
+            }
+          }
+          fcnt[size_t(b) * TP + tt] = ko;
+          kout = ko;
+        } else {
+          uint64_t pk[KEEP];
+          float pg[KEEP];
+          uint32_t kp = 0;
+          if (L == Lt) {  // covering lists of an earlier launch
+            const int pi = i >> 1, pj = j >> 1;
+            uint32_t pb = 0;
+            int pt = 0;
+            const bool pin = pi < layer_dim(c.W, L + 1) && pj < layer_dim(c.H, L + 1);
+            if (pin) texel_bin(P, v, L + 1, pi, pj, pb, pt);
+            const uint32_t pc = pin ? fcnt[size_t(pb) * TP + pt] : 0u;
+            kp = (pc & 31u) + ((pc >> 5) & 31u);
+#pragma unroll
+            for (int m = 0; m < KEEP; ++m) {
+              pk[m] = fkey[(size_t(pb) * KEEP + m) * TP + pt];
+              pg[m] = fgam[(size_t(pb) * KEEP + m) * TP + pt];
+            }
+          } else {  // the block of layer L + 1 above, from LDS
+            const int q = ((j >> 1) - ty * (rh >> 1)) * (rw >> 1) + ((i >> 1) - tx * (rw >> 1));
+            kp = s_n[prev][q];
+#pragma unroll
+            for (int m = 0; m < KEEP; ++m) {
+              pk[m] = s_k[prev][m][q];
+              pg[m] = s_g[prev][m][q];
+            }
+          }
+          // stable merge of the two sorted lists, own first on equal keys
+          uint32_t io = 0, ip = 0, mask = 0;
+#pragma unroll
+          for (int m = 0; m < KEEP; ++m) {
+            uint64_t okm = KEY_NONE, pkm = KEY_NONE;
+            float ogm = 0.0f, pgm = 0.0f;
+#pragma unroll
+            for (int r = 0; r < KEEP; ++r) {  // register lists: select slots io and ip
+              okm = uint32_t(r) == io ? ok[r] : okm;
+              ogm = uint32_t(r) == io ? og[r] : ogm;
+              pkm = uint32_t(r) == ip ? pk[r] : pkm;
+              pgm = uint32_t(r) == ip ? pg[r] : pgm;
+            }
+            const uint64_t okv = io < ko ? okm : KEY_NONE;
+            const uint64_t pkv = ip < kp ? pkm : KEY_NONE;
+            const bool take_o = io < ko && !(pkv < okv);
+            const bool take_p = !take_o && ip < kp;
+            fk[m] = take_o ? okv : (take_p ? pkv : KEY_NONE);
+            fg[m] = take_o ? ogm : (take_p ? pgm : 0.0f);
+            mask |= (take_p ? 1u : 0u) << m;
+            io += take_o ? 1u : 0u;
+            ip += take_p ? 1u : 0u;
+          }
+          kout = io + ip;
+          float C[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) C[d] = 0.0f;
+          float T = 1.0f;
+          constexpr int GB = D > 4 ? 4 : 8;
+          if (P.n > 0) {  // without points every list is empty and there is no point 0
+#pragma unroll
+            for (int m0 = 0; m0 < KEEP; m0 += GB) {
+              float4 tv[GB][D / 4];
+#pragma unroll
+              for (int r = 0; r < GB; ++r) {
+                const int m = m0 + r;
+                const uint32_t id = uint32_t(m) < kout ? uint32_t(fk[m]) : 0u;
+                const float4* tp = reinterpret_cast<const float4*>(desc + size_t(id) * D);
+#pragma unroll
+                for (int e = 0; e < D / 4; ++e) tv[r][e] = tp[e];
+              }
+#pragma unroll
+              for (int r = 0; r < GB; ++r) {
+                const int m = m0 + r;
+                if (uint32_t(m) < kout) {
+                  const float w = T * fg[m];
+#pragma unroll
+                  for (int e = 0; e < D / 4; ++e) {
+                    C[4 * e + 0] += w * tv[r][e].x;
+                    C[4 * e + 1] += w * tv[r][e].y;
+                    C[4 * e + 2] += w * tv[r][e].z;
+                    C[4 * e + 3] += w * tv[r][e].w;
+                  }
+                  T = T * (1.0f - fg[m]);
+                }
+              }
+            }
+          }
+          if (L > 0) {  // (layer 0's lists are rebuilt where they are read)
+#pragma unroll
+            for (int m = 0; m < KEEP; ++m)
+              if (uint32_t(m) < kout) {
+                fkey[(tb + m) * TP + tt] = fk[m];
+                fgam[(tb + m) * TP + tt] = fg[m];
+              }
+          }
+          fcnt[size_t(b) * TP + tt] = io | (ip << 5) | (mask << 16);
+          write_texel<D>(C, T, size_t(c.lout[L]) + size_t(j) * WL + i, pyr, bg, alpha);
+        }
+      }
+      if (k > 0) {  // the next finer layer reads this block's lists
+#pragma unroll
+        for (int m = 0; m < KEEP; ++m) {
+          s_k[cur][m][t] = uint32_t(m) < kout ? fk[m] : KEY_NONE;
+          s_g[cur][m][t] = uint32_t(m) < kout ? fg[m] : 0.0f;
+        }
+        s_n[cur][t] = kout;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Slot m of the blended list of texel (b, t), as the forward pass made it: stored in fkey /
+// fgam, or (layer 0 below a coarser layer, whose lists are not stored) rebuilt from the own
+// list (kkey / kgam of the texel) and the covering texel's stored list (pb, pt): by the
+// origin mask, slot m is the covering list's item popc(mask below m), else the own list's
+// item m minus that.  Every address is in bounds whatever m.
+struct BlendedSrc {
+  const uint64_t* fkey;
+  const float* fgam;
+  const uint64_t* kkey;  // null: the list is stored
+  const float* kgam;
+  uint32_t pb;
+  int pt;
+};
+__device__ __forceinline__ void blended_slot(const BlendedSrc& S, uint32_t b, int t, uint32_t fc,
+                                             int m, uint64_t& key, float& gam) {
+  if (!S.kkey) {
+    const size_t o = (size_t(b) * KEEP + m) * TP + t;
+    key = S.fkey[o];
+    gam = S.fgam[o];
+    return;
+  }
+  const uint32_t mask = fc >> 16;
+  const uint32_t ip = __popc(mask & ((1u << m) - 1u));
+  const bool up = (mask >> m) & 1u;
+  const size_t o = up ? (size_t(S.pb) * KEEP + ip) * TP + S.pt
+                      : (size_t(b) * KEEP + (uint32_t(m) - ip)) * TP + t;
+  key = up ? S.fkey[o] : S.kkey[o];
+  gam = up ? S.fgam[o] : S.kgam[o];
 }
 
 // Blend adjoint of the blended list of one texel (tile b, slot t, pyramid texel tex; fc its
@@ -1910,14 +2139,12 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
 // k); writes the background gradient.  Returns k.  has_points: the cloud is not empty (an
 // empty slot then reads point 0's descriptor, which exists).
 template <int D>
-__device__ __forceinline__ uint32_t blended_adjoint(const uint64_t* __restrict__ fkey,
-                                                    const float* __restrict__ fgam, uint32_t b,
+__device__ __forceinline__ uint32_t blended_adjoint(const BlendedSrc& S, uint32_t b,
                                                     int t, uint32_t fc, size_t tex, bool has_points,
                                                     const float* __restrict__ desc,
                                                     const float* __restrict__ gpyr, const Extras& X,
                                                     float (&G)[D], float (&dg)[KEEP],
                                                     float (&tg)[KEEP]) {
-  const size_t tb = size_t(b) * KEEP;
   const uint32_t k = (fc & 31u) + ((fc >> 5) & 31u);
   {
     const float4* gp = reinterpret_cast<const float4*>(gpyr + tex * D);
@@ -1931,9 +2158,9 @@ __device__ __forceinline__ uint32_t blended_adjoint(const uint64_t* __restrict__
   uint32_t idx[KEEP];
 #pragma unroll
   for (int m = 0; m < KEEP; ++m) {  // every slot is read (in bounds), those past k dropped
-    const size_t ko = (tb + m) * TP + t;
-    const uint64_t kr = fkey[ko];
-    const float gr = fgam[ko];
+    uint64_t kr;
+    float gr;
+    blended_slot(S, b, t, fc, m, kr, gr);
     const bool ok = uint32_t(m) < k;
     idx[m] = ok ? uint32_t(kr) : 0u;
     gam[m] = ok ? gr : 0.0f;
@@ -2013,8 +2240,8 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   const uint32_t mask = fc >> 16;
   const size_t tex = size_t(c.lout[L]) + size_t(j) * WL + i;
   float G[D], dg[KEEP], tg[KEEP];
-  const uint32_t k = blended_adjoint<D>(fkey, fgam, b, t, fc, tex, P.n > 0, desc, gpyr, X, G, dg,
-                                        tg);
+  const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
+  const uint32_t k = blended_adjoint<D>(src, b, t, fc, tex, P.n > 0, desc, gpyr, X, G, dg, tg);
   // the finer texels this texel covers, and how many of its items each of them took
   size_t cbase[4];
   uint32_t cup[4];
@@ -2072,6 +2299,169 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   }
 }
 
+// incl_bwd_group: layers Lb..Lt in one launch (Lt - Lb at most log2 of the tile's shorter
+// side), finest first, one workgroup per tile of layer Lb (grid.y = view); the texels of
+// layer Lb + k over the tile form a (tw >> k) x (th >> k) block over no other tile.  Every
+// texel's total per item is its own blend part, then what each of its four finer texels
+// passed up, in child order (as k_incl_bwd): the own parts of the layers above Lb are put
+// in LDS first; then, layer by layer, each texel completes its totals, writes its own
+// items' totals to itot and adds its items of the coarser list to its covering texel's LDS
+// totals, one child position at a time.  Layer Lb reads what layer Lb - 1 passed up from
+// memory; layer Lt passes its coarser items up through memory (iup).
+constexpr int GROUP_PARENTS = 64 + 16 + 4 + 1;  // texels of the layers above a 16x16 tile
+template <int D>
+__global__ __launch_bounds__(256) void k_incl_bwd_group(
+    const Params P, int Lb, int Lt, const uint64_t* __restrict__ fkey,
+    const float* __restrict__ fgam, const uint32_t* __restrict__ fcnt,
+    const float* __restrict__ desc, const float* __restrict__ gpyr, float* __restrict__ itot,
+    float* __restrict__ iup, const Extras X) {
+  constexpr int S = D + 1;
+  __shared__ float s_tot[GROUP_PARENTS][KEEP][S];
+  const int v = blockIdx.y;
+  const ViewP& c = P.view[v];
+  const uint32_t local = blockIdx.x;
+  if (local >= c.lbin[Lb + 1] - c.lbin[Lb]) return;  // uniform per workgroup
+  const int t = threadIdx.x;
+  const int ltw = P.ltw, lth = 8 - P.ltw;
+  const int tiles_x = (layer_dim(c.W, Lb) + (1 << ltw) - 1) >> ltw;
+  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
+  // block k's first slot in s_tot (layer Lb + k, k >= 1)
+  auto slot0 = [](int k) { int o = 0; for (int q = 1; q < k; ++q) o += TP >> (2 * q); return o; };
+  // the texel of this workgroup's block of layer Lb + k handled by thread t (false: none)
+  auto texel_of = [&](int k, int& i, int& j, int& WL, int& HL) {
+    const int rw = (1 << ltw) >> k, rh = (1 << lth) >> k;
+    if (t >= rw * rh) return false;
+    i = tx * rw + t % rw;
+    j = ty * rh + t / rw;
+    WL = layer_dim(c.W, Lb + k);
+    HL = layer_dim(c.H, Lb + k);
+    return i < WL && j < HL;
+  };
+  // own parts of the layers above Lb
+  for (int k = 1; k <= Lt - Lb; ++k) {
+    int i, j, WL, HL;
+    const bool in = texel_of(k, i, j, WL, HL);
+    if (t < (TP >> (2 * k))) {
+      float (*tot)[S] = s_tot[slot0(k) + t];
+      float G[D], dg[KEEP], tg[KEEP];
+#pragma unroll
+      for (int d = 0; d < D; ++d) G[d] = 0.0f;
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) { dg[m] = 0.0f; tg[m] = 0.0f; }
+      if (in) {
+        uint32_t b;
+        int tt;
+        texel_bin(P, v, Lb + k, i, j, b, tt);
+        const uint32_t fc = fcnt[size_t(b) * TP + tt];
+        blended_adjoint<D>(src, b, tt, fc, size_t(c.lout[Lb + k]) + size_t(j) * WL + i, P.n > 0,
+                           desc, gpyr, X, G, dg, tg);
+      }
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) {
+        tot[m][0] = dg[m];
+#pragma unroll
+        for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k <= Lt - Lb; ++k) {
+    const int L = Lb + k;
+    int i = 0, j = 0, WL = 0, HL = 0;
+    const bool in = texel_of(k, i, j, WL, HL);
+    float tot[KEEP][S];
+    uint32_t kk = 0, mask = 0, b = 0;
+    int tt = 0;
+    if (in) {
+      texel_bin(P, v, L, i, j, b, tt);
+      const uint32_t fc = fcnt[size_t(b) * TP + tt];
+      mask = fc >> 16;
+      kk = (fc & 31u) + ((fc >> 5) & 31u);
+      if (k == 0) {  // own part, then what layer L - 1 passed up (memory, an earlier launch)
+        float G[D], dg[KEEP], tg[KEEP];
+        blended_adjoint<D>(src, b, tt, fc, size_t(c.lout[L]) + size_t(j) * WL + i, P.n > 0, desc,
+                           gpyr, X, G, dg, tg);
+#pragma unroll
+        for (int m = 0; m < KEEP; ++m) {
+          tot[m][0] = dg[m];
+#pragma unroll
+          for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
+        }
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {
+          const int ci = 2 * i + (q & 1), cj = 2 * j + (q >> 1);
+          if (!(ci < layer_dim(c.W, L - 1) && cj < layer_dim(c.H, L - 1))) continue;
+          uint32_t cb;
+          int ct;
+          texel_bin(P, v, L - 1, ci, cj, cb, ct);
+          const uint32_t cup = (fcnt[size_t(cb) * TP + ct] >> 5) & 31u;
+          const size_t cbase = size_t(cb) * KEEP * S * TP + size_t(ct);
+#pragma unroll
+          for (int m = 0; m < KEEP; ++m) {
+            const bool take = uint32_t(m) < cup;
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+              const float u = iup[cbase + (size_t(m) * S + r) * TP];
+              tot[m][r] += take ? u : 0.0f;
+            }
+          }
+        }
+      } else {  // own part and every child's, already summed in LDS
+        const float (*st)[S] = s_tot[slot0(k) + t];
+#pragma unroll
+        for (int m = 0; m < KEEP; ++m)
+#pragma unroll
+          for (int r = 0; r < S; ++r) tot[m][r] = st[m][r];
+      }
+      // own items to their slots; coarser items up (through memory from the top layer)
+      const size_t tb = size_t(b) * KEEP;
+      uint32_t so = 0, sp = 0;
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) {
+        if (uint32_t(m) < kk) {
+          const bool up = (mask >> m) & 1u;
+          if (!up) {
+            float* dst = itot + ((tb + so) * S) * TP + tt;
+#pragma unroll
+            for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
+            ++so;
+          } else {
+            if (k == Lt - Lb) {
+              float* dst = iup + ((tb + sp) * S) * TP + tt;
+#pragma unroll
+              for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
+            }
+            ++sp;
+          }
+        }
+      }
+    }
+    if (k < Lt - Lb) {  // coarser items to the covering texel's totals, one child position at a time
+      const int rw = (1 << ltw) >> k;
+      const int q = (t / rw & 1) * 2 + (t % rw & 1);  // position among the covering texel's four
+      const int pq = (t / rw >> 1) * (rw >> 1) + (t % rw >> 1);
+#pragma unroll 1
+      for (int qd = 0; qd < 4; ++qd) {
+        __syncthreads();
+        if (in && q == qd) {
+          float (*pt)[S] = s_tot[slot0(k + 1) + pq];
+          uint32_t sp = 0;
+#pragma unroll
+          for (int m = 0; m < KEEP; ++m) {
+            if (uint32_t(m) < kk && ((mask >> m) & 1u)) {
+#pragma unroll
+              for (int r = 0; r < S; ++r) pt[sp][r] += tot[m][r];
+              ++sp;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // incl_bwd01: layers 0 and 1 in one launch, one workgroup per tile of layer 1.  Each thread
 // runs the blend adjoint of its layer-1 texel and then of the four layer-0 texels it covers,
 // whose items taken from it are added to its totals straight from registers (through a
@@ -2080,6 +2470,7 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
 template <int D>
 __global__ __launch_bounds__(256) void k_incl_bwd01(
     const Params P, const uint64_t* __restrict__ fkey, const float* __restrict__ fgam,
+    const uint64_t* __restrict__ kkey, const float* __restrict__ kgam,
     const uint32_t* __restrict__ fcnt, const float* __restrict__ desc,
     const float* __restrict__ gpyr, float* __restrict__ itot, float* __restrict__ iup_out,
     const Extras X) {
@@ -2107,8 +2498,9 @@ __global__ __launch_bounds__(256) void k_incl_bwd01(
   uint32_t k;
   {
     float G[D], dg[KEEP], tg[KEEP];
-    k = blended_adjoint<D>(fkey, fgam, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i,
-                           P.n > 0, desc, gpyr, X, G, dg, tg);
+    const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
+    k = blended_adjoint<D>(src, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, P.n > 0,
+                           desc, gpyr, X, G, dg, tg);
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) {
       tot[m][0] = dg[m];
@@ -2126,7 +2518,9 @@ __global__ __launch_bounds__(256) void k_incl_bwd01(
     const uint32_t cfc = fcnt[size_t(cb) * TP + ct];
     const uint32_t cmask = cfc >> 16;
     float G[D], dg[KEEP], tg[KEEP];
-    const uint32_t ck = blended_adjoint<D>(fkey, fgam, cb, ct, cfc,
+    // layer 0's lists are rebuilt from their own lists and this texel's (b, t)
+    const BlendedSrc csrc{fkey, fgam, kkey, kgam, b, t};
+    const uint32_t ck = blended_adjoint<D>(csrc, cb, ct, cfc,
                                            size_t(c.lout[0]) + size_t(cj) * W0 + ci, P.n > 0, desc,
                                            gpyr, X, G, dg, tg);
     const size_t ctb = size_t(cb) * KEEP;
@@ -2728,7 +3122,20 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     uint64_t* fkey = reinterpret_cast<uint64_t*>(sv + lay.s_fkey);
     float* fgam = reinterpret_cast<float*>(sv + lay.s_fgam);
     uint32_t* fcnt = reinterpret_cast<uint32_t*>(sv + lay.s_fcnt);
-    for (int L = P.nl - 1; L >= 0; --L) {
+    // layers 3 and up in groups of up to 1 + log2(shorter tile side) layers, coarsest group
+    // first, each one launch over the tiles of its finest layer; layers 0-2 (nearly all of
+    // the texels) keep one launch each
+    const int gmax = 1 + std::min(P.ltw, 8 - P.ltw);
+    int L = P.nl - 1;
+    while (L >= 3) {
+      const int Lb = std::max(3, L - gmax + 1);
+      hipLaunchKernelGGL(k_incl_fwd_group<D>, dim3(layer_tiles_max(P, Lb), uint32_t(P.V)),
+                         dim3(256), 0, st, P, Lb, L, npix, kkey, kgam, fkey, fgam, fcnt,
+                         pts.desc, pyr, X.bg, X.alpha);
+      TRIPS_HIP(hipGetLastError());
+      L = Lb - 1;
+    }
+    for (; L >= 0; --L) {
       hipLaunchKernelGGL(k_incl_fwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256), 0,
                          st, P, L, npix, kkey, kgam, fkey, fgam, fcnt, pts.desc, pyr, X.bg,
                          X.alpha);
@@ -2769,12 +3176,24 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
       const bool fuse = P.nl > 1;
       if (fuse) {
         hipLaunchKernelGGL(k_incl_bwd01<D>, dim3(layer_tiles_max(P, 1), uint32_t(P.V)), dim3(256),
-                           0, st, P, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, X);
+                           0, st, P, fkey, fgam, kkey, kgam, fcnt, pts.desc, gpyr, itot, iup, X);
         TRIPS_HIP(hipGetLastError());
       }
-      for (int L = fuse ? 2 : 0; L < P.nl; ++L) {
-        hipLaunchKernelGGL(k_incl_bwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256), 0,
-                           st, P, L, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, iup, X);
+      // layers 2 and below (when not fused) one launch each; from layer 3 on, groups of up to
+      // 1 + log2(shorter tile side) layers as one launch over their finest layer's tiles
+      const int gmax = std::min(1 + std::min(P.ltw, 8 - P.ltw), 5);
+      for (int L = fuse ? 2 : 0; L < P.nl;) {
+        if (L < 3) {
+          hipLaunchKernelGGL(k_incl_bwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256),
+                             0, st, P, L, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, iup, X);
+          ++L;
+        } else {
+          const int Lt = std::min(P.nl - 1, L + gmax - 1);
+          hipLaunchKernelGGL(k_incl_bwd_group<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)),
+                             dim3(256), 0, st, P, L, Lt, fkey, fgam, fcnt, pts.desc, gpyr, itot,
+                             iup, X);
+          L = Lt + 1;
+        }
         TRIPS_HIP(hipGetLastError());
       }
     }
