@@ -1,7 +1,8 @@
 """Benchmark: splatted points per second for forward+backward trilinear point splatting.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                [--no-coarser] [--no-optim] [--no-8m] [--no-decoder] [--opt-iters N]
+                [--no-coarser] [--no-optim] [--no-8m] [--no-decoder] [--no-extras]
+                [--opt-iters N]
 
 Headline workload (one step = the whole hot path once): 2M points drawn from 64 anisotropic
 Gaussian clusters plus 30% on planar patches, one 1920x1080 pinhole view, 8 pyramid layers,
@@ -309,11 +310,13 @@ def run_forward_only(torch, tp, r, pargs, pyr, w, steps, workers_sc=None):
 
 def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev, ms_plain):
     """The headline workload with coarser-layer inclusion: graph-replayed steps, then eager
-    steps with per-kernel events.  The inclusion passes are charged their algorithmic bytes:
-    forward, per texel the own kept fragments read (12 B), every blended item written and
-    its descriptor gathered (12 + 4D B) plus the texel (4D B) and its count (4 B); backward,
-    every blended item read with its descriptor (12 + 4D B) and its totals written and read
-    once more (8 (1 + D) B), plus the upstream gradient (4D B) and the count (4 B)."""
+    steps with per-kernel events.  The inclusion passes are charged the bytes of their own data
+    structures (an implementation model: the paper gives the variant no byte count): forward,
+    per texel the own kept fragments read (12 B), every blended item's descriptor gathered
+    (4D B) and, above layer 0 (whose lists are rebuilt where read), written (12 B), plus the
+    texel (4D B) and its count (4 B); backward, every blended item read (12 B) with its
+    descriptor (4D B) and its totals written and read once more (8 (1 + D) B), plus the
+    upstream gradient (4D B) and the count (4 B)."""
     cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
     N = len(sc["points"]["x"])
     r = tp.Renderer([cam], nl, D, N, device=dev, include_coarser=True)
@@ -328,6 +331,7 @@ def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev, ms_plain):
     K = int(torch.clamp(c64, max=tp.KEEP).sum().item())
     Fb = int((ids >= 0).sum().item())
     P = r.texels
+    Fb0 = int((ids[:r.layouts[0][1][1]] >= 0).sum().item())  # blended items of layer 0
 
     def eager():
         r.forward(*pargs, out=pyr)
@@ -337,15 +341,15 @@ def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev, ms_plain):
     ms_eager = timed(torch, eager, steps)
     ms = min(ms_graph, ms_eager)
     stage_ms, _ = stage_times(torch, tp, eager, steps)
-    ib = {"incl_fwd": 12 * K + (12 + 4 * D) * Fb + (4 * D + 4) * P,
+    ib = {"incl_fwd": 12 * K + 4 * D * Fb + 12 * (Fb - Fb0) + (4 * D + 4) * P,
           "incl_bwd": (12 + 4 * D + 8 * (1 + D)) * Fb + (4 * D + 4) * P}
     return {"workload": "clusters2m_1920x1080_8layers_d4_fwd_bwd_coarser_inclusion",
             "ms_per_step": ms, "ms_per_step_graph": ms_graph, "ms_per_step_eager": ms_eager,
             "inclusion_overhead_ms": ms - ms_plain,
             "points_per_s": N / (ms / 1e3), "blended_items": Fb,
             "blended_items_plain": K, "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
-            "incl_gbps": {k: round(b / (stage_ms[k] / 1e3) / 1e9, 1) for k, b in ib.items()
-                          if k in stage_ms}}
+            "incl_impl_gbps": {k: round(b / (stage_ms[k] / 1e3) / 1e9, 1) for k, b in ib.items()
+                               if k in stage_ms}}
 
 
 def run_points_8m(torch, tp, scenes, steps, warmup, dev):
@@ -624,6 +628,8 @@ def main():
     ap.add_argument("--no-optim", action="store_true")
     ap.add_argument("--no-8m", action="store_true")
     ap.add_argument("--no-decoder", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the copy, forward-only and 4096-point sections (profiling runs)")
     ap.add_argument("--opt-iters", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference for "
@@ -729,13 +735,14 @@ def main():
         "fine_tile_entries": w["E_f"], "fine_tile_fragments": w["F_f"],
         "fine_tile_kept": w["K_f"], "work_items": w["I_c"],
     }
-    log("plain device copy")
-    out["copy"] = run_copy(torch, dev)
-    log("forward alone")
-    out["forward_only"] = run_forward_only(torch, tp, r, pargs, pyr, w, args.steps,
-                                           None if args.no_cpu_baseline else sc)
-    log("4096 points at 256x256")
-    out["small"] = run_small_latency(torch, tp, scenes, args.steps, dev)
+    if not args.no_extras:
+        log("plain device copy")
+        out["copy"] = run_copy(torch, dev)
+        log("forward alone")
+        out["forward_only"] = run_forward_only(torch, tp, r, pargs, pyr, w, args.steps,
+                                               None if args.no_cpu_baseline else sc)
+        log("4096 points at 256x256")
+        out["small"] = run_small_latency(torch, tp, scenes, args.steps, dev)
     if not args.no_decoder:
         log("reconstruction network on the rendered pyramid")
         r.forward(*pargs, out=pyr)

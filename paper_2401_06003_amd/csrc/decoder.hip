@@ -18,9 +18,10 @@
 //    ceil(9 D / 32) steps over (tap, layer channel), so every A fragment is one or two
 //    LDS reads at 16-byte granularity; B fragments are stored lane-major (packed once by
 //    k_dec_pack) and read without bank conflicts;
-//  - a wave owns four rows of the tile: 4 x 4 accumulator tiles of 16 texels x 16 outputs;
-//    outputs 16j + lane%16 (feature, j = 0, 1) and 32 + 16j + lane%16 (gate) sit in the same
-//    lane, so the gating needs no exchange;
+//  - a wave owns four rows of the tile: 4 x 4 accumulator tiles of 16 outputs x 16 texels
+//    (kernel fragments as the A operand); outputs 16j + 4(lane/16) + i (feature, j = 0, 1)
+//    and 32 + the same (gate) of texel lane%16 sit in the same lane, so the gating needs no
+//    exchange and every lane reads and writes four consecutive channels at once;
 //  - the epilogue gates, adds the bypass, rounds to binary16 and writes the tile through LDS
 //    in 16-byte rows (or applies the output layer and writes float32).
 #include <hip/hip_runtime.h>
@@ -44,6 +45,8 @@ constexpr int TILE = 16;                  // output tile is TILE x TILE texels
 constexpr int HALO = TILE + 2;
 constexpr int HPIX = HALO * HALO;         // 324 halo texels
 constexpr int PSTRIDE = 40;               // halves per halo texel: 32 doubled + 8 layer channels
+constexpr int CREG = TILE / 2 + 2;        // coarser texels under the halo, per row and column
+constexpr int OSTRIDE = 40;               // halves per texel of the output staging (32 used)
 constexpr int DEC_THREADS = 256;
 constexpr int MAX_OUT = 8;
 constexpr int MAXL = TRIPS_MAX_LAYERS;
@@ -140,10 +143,13 @@ __global__ void k_dec_pack_out(const float* __restrict__ wo, const float* __rest
 }
 
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ float elu_f(float x) { return x > 0.0f ? x : expm1f(x); }
+// The gating's exponentials use the hardware exp2 (a few float32 ulps): the results are
+// rounded to binary16, whose spacing is 2^13 float32 ulps.
+__device__ __forceinline__ float elu_f(float x) { return x > 0.0f ? x : __expf(x) - 1.0f; }
 __device__ __forceinline__ float sigmoid_f(float x) {
-  const float e = expf(-fabsf(x));
-  return x >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+  const float e = __expf(-fabsf(x));
+  const float r = __builtin_amdgcn_rcpf(1.0f + e);  // (the hardware reciprocal, 1 ulp)
+  return x >= 0.0f ? r : e * r;
 }
 
 // Doubling along one axis: finer index i sits at coarser position i/2 - 1/4: the nearer
@@ -155,88 +161,147 @@ __device__ __forceinline__ void up_taps(int i, int n, int& near, int& far) {
   far = min(max((i & 1) ? k + 1 : k - 1, 0), n - 1);
 }
 
-template <int D, bool COARSE, bool FINAL>
-__global__ __launch_bounds__(DEC_THREADS) void k_dec_block(
+// FO: 0 = write the block output; 3 = apply a 3-channel output layer; MAX_OUT = apply an
+// output layer of out_dim <= MAX_OUT channels (zero padded)
+template <int D, bool COARSE, int FO>
+__global__ __launch_bounds__(DEC_THREADS, 2) void k_dec_block(
     const float* __restrict__ feat, const uint16_t* __restrict__ coarse,
     const uint16_t* __restrict__ packed, const float* __restrict__ outw, int W, int H, int Wc,
     int Hc, int out_dim, uint16_t* __restrict__ hout, float* __restrict__ image) {
   constexpr int STEPS = conv_steps(D, COARSE);
   constexpr int S0 = COARSE ? 9 : 0;
-  __shared__ __align__(16) half8 s_b[STEPS * 4 * 64];
+  // B fragments; of the last step only lanes 0..15 hold K indices below 9 D (both for D = 4
+  // and D = 8), so only those are staged
+  __shared__ __align__(16) half8 s_b[(STEPS - 1) * 4 * 64 + 4 * 16];
   __shared__ __align__(16) _Float16 s_in[HPIX * PSTRIDE];  // also the output staging
+  __shared__ __align__(16) half8 s_c[COARSE ? CREG * CREG * 4 : 4];  // coarser texels under the halo
   __shared__ float s_bias[NOUT];
+  constexpr bool FINAL = FO > 0;
+  __shared__ float s_ow[FINAL ? (FEAT + 1) * FO : 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   {  // the packed kernel, once per workgroup
     const uint4* src = reinterpret_cast<const uint4*>(packed);
     uint4* dst = reinterpret_cast<uint4*>(s_b);
-    for (int i = t; i < STEPS * 256; i += DEC_THREADS) dst[i] = src[i];
+    for (int i = t; i < (STEPS - 1) * 256; i += DEC_THREADS) dst[i] = src[i];
+    if (t < 64) dst[(STEPS - 1) * 256 + t] = src[(STEPS - 1) * 256 + (t >> 4) * 64 + (t & 15)];
     const float* pb = reinterpret_cast<const float*>(reinterpret_cast<const char*>(packed) +
                                                      packed_kernel_bytes(D, COARSE));
     if (t < NOUT) s_bias[t] = pb[t];
+    if (FINAL) {  // output layer [c][k] padded to FO outputs (zeros), then its bias
+      for (int u = t; u < (FEAT + 1) * FO; u += DEC_THREADS) {
+        const int c = u / FO, k = u % FO;
+        s_ow[u] = k < out_dim ? outw[c * out_dim + k] : 0.0f;
+      }
+    }
   }
   const int tx_n = (W + TILE - 1) / TILE, ty_n = (H + TILE - 1) / TILE;
   const int tiles = tx_n * ty_n;
+  // ---- halo, phase 1: every global load of a tile issued at once, into registers (the next
+  // tile's while this one is on the matrix cores).  The coarser block's texels under the
+  // halo (rows and columns (y0 >> 1) - 1 .. + CREG - 1, clamped to the layer on load) go to
+  // LDS as they are; the layer's features go to the halo as binary16.
+  half8 cv[2];
+  float4 fv[2][D / 4];
+  auto fetch = [&](int tile) {
+    const int y0 = (tile / tx_n) * TILE, x0 = (tile % tx_n) * TILE;
+    const int cy0 = (y0 >> 1) - 1, cx0 = (x0 >> 1) - 1;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int u = t + r * DEC_THREADS;
+      if (COARSE && u < CREG * CREG * 4) {
+        const int p = u >> 2, g = u & 3;
+        const int cy = min(max(cy0 + p / CREG, 0), Hc - 1);
+        const int cx = min(max(cx0 + p % CREG, 0), Wc - 1);
+        cv[r] = reinterpret_cast<const half8*>(coarse)[(size_t(cy) * Wc + cx) * 4 + g];
+      }
+      if (u < HPIX) {
+        const int y = y0 + u / HALO - 1, x = x0 + u % HALO - 1;
+        const bool in = y >= 0 && y < H && x >= 0 && x < W;
+        const float4* fp =
+            reinterpret_cast<const float4*>(feat + (size_t(in ? y : 0) * W + (in ? x : 0)) * D);
+#pragma unroll
+        for (int q = 0; q < D / 4; ++q) fv[r][q] = in ? fp[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  };
+  if (int(blockIdx.x) < tiles) fetch(blockIdx.x);
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int y0 = (tile / tx_n) * TILE, x0 = (tile % tx_n) * TILE;
+    const int cy0 = (y0 >> 1) - 1, cx0 = (x0 >> 1) - 1;
     __syncthreads();  // previous tile's staging is consumed (and the kernel is in LDS)
-    // ---- halo: 324 texels x (4 groups of 8 doubled channels, plus the layer channels)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int u = t + r * DEC_THREADS;
+      if (COARSE && u < CREG * CREG * 4) s_c[u] = cv[r];
+      if (u < HPIX) {
+        half8 h;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float4 v = q < D / 4 ? fv[r][q < D / 4 ? q : 0] : make_float4(0.f, 0.f, 0.f, 0.f);
+          h[4 * q + 0] = _Float16(v.x); h[4 * q + 1] = _Float16(v.y);
+          h[4 * q + 2] = _Float16(v.z); h[4 * q + 3] = _Float16(v.w);
+        }
+        reinterpret_cast<half8*>(s_in + u * PSTRIDE)[4] = h;
+      }
+    }
+    __syncthreads();
+    // ---- halo, phase 2: the doubled features of the 324 halo texels, from LDS
     for (int u = t; u < HPIX * 4; u += DEC_THREADS) {
       const int p = u >> 2, g = u & 3;
       const int y = y0 + p / HALO - 1, x = x0 + p % HALO - 1;
       half8 hv;
 #pragma unroll
       for (int e = 0; e < 8; ++e) hv[e] = _Float16(0.0f);
-      half8 fv = hv;
-      if (y >= 0 && y < H && x >= 0 && x < W) {
-        if (COARSE) {
-          int ny, fy, nx, fx;
-          up_taps(y, Hc, ny, fy);
-          up_taps(x, Wc, nx, fx);
-          const half8* c8 = reinterpret_cast<const half8*>(coarse);
-          const half8 a = c8[(size_t(ny) * Wc + nx) * 4 + g];  // (near y, near x)
-          const half8 b = c8[(size_t(fy) * Wc + nx) * 4 + g];  // (far y, near x)
-          const half8 c = c8[(size_t(ny) * Wc + fx) * 4 + g];  // (near y, far x)
-          const half8 d = c8[(size_t(fy) * Wc + fx) * 4 + g];  // (far y, far x)
+      if (COARSE && y >= 0 && y < H && x >= 0 && x < W) {
+        int ny, fy, nx, fx;
+        up_taps(y, Hc, ny, fy);
+        up_taps(x, Wc, nx, fx);
+        ny -= cy0; fy -= cy0; nx -= cx0; fx -= cx0;  // inside the staged region
+        const half8 a = s_c[(ny * CREG + nx) * 4 + g];  // (near y, near x)
+        const half8 b = s_c[(fy * CREG + nx) * 4 + g];  // (far y, near x)
+        const half8 c = s_c[(ny * CREG + fx) * 4 + g];  // (near y, far x)
+        const half8 d = s_c[(fy * CREG + fx) * 4 + g];  // (far y, far x)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            // rows first, then columns, each 3/4 near + 1/4 far
-            const float cn = fmaf(0.75f, float(a[e]), 0.25f * float(b[e]));
-            const float cf = fmaf(0.75f, float(c[e]), 0.25f * float(d[e]));
-            hv[e] = _Float16(fmaf(0.75f, cn, 0.25f * cf));
-          }
-        }
-        if (g == 0) {
-          const float* fp = feat + (size_t(y) * W + x) * D;
-          if (D == 4) {
-            const float4 v = *reinterpret_cast<const float4*>(fp);
-            fv[0] = _Float16(v.x); fv[1] = _Float16(v.y); fv[2] = _Float16(v.z); fv[3] = _Float16(v.w);
-          } else {
-            const float4 v0 = reinterpret_cast<const float4*>(fp)[0];
-            const float4 v1 = reinterpret_cast<const float4*>(fp)[1];
-            fv[0] = _Float16(v0.x); fv[1] = _Float16(v0.y); fv[2] = _Float16(v0.z); fv[3] = _Float16(v0.w);
-            fv[4] = _Float16(v1.x); fv[5] = _Float16(v1.y); fv[6] = _Float16(v1.z); fv[7] = _Float16(v1.w);
-          }
+        for (int e = 0; e < 8; ++e) {
+          // rows first, then columns, each 3/4 near + 1/4 far
+          const float cn = fmaf(0.75f, float(a[e]), 0.25f * float(b[e]));
+          const float cf = fmaf(0.75f, float(c[e]), 0.25f * float(d[e]));
+          hv[e] = _Float16(fmaf(0.75f, cn, 0.25f * cf));
         }
       }
-      half8* row = reinterpret_cast<half8*>(s_in + p * PSTRIDE);
-      row[g] = hv;
-      if (g == 0) row[4] = fv;
+      reinterpret_cast<half8*>(s_in + p * PSTRIDE)[g] = hv;
     }
     __syncthreads();
+    if (tile + int(gridDim.x) < tiles) fetch(tile + gridDim.x);  // in flight during the MFMAs
     // ---- implicit GEMM: wave owns tile rows 4 wave .. 4 wave + 3
+    // The kernel fragments go in as the A operand and the texels as B, so the accumulator is
+    // the transposed tile: lane (grp, col) holds outputs 16 j + 4 grp + i of texel col.
+    const int col = lane & 15, grp = lane >> 4;
     floatx4 acc[4][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float bj = s_bias[16 * j + (lane & 15)];
+      floatx4 bj;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r][j] = floatx4{bj, bj, bj, bj};
+      for (int i = 0; i < 4; ++i) bj[i] = s_bias[16 * j + 4 * grp + i];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r][j] = bj;
     }
-    const int col = lane & 15, grp = lane >> 4;
-#pragma unroll 1
+#pragma unroll
     for (int s = 0; s < STEPS; ++s) {
       half8 b[4];
+      if (s < STEPS - 1) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = s_b[(s * 4 + j) * 64 + lane];
+        for (int j = 0; j < 4; ++j) b[j] = s_b[(s * 4 + j) * 64 + lane];
+      } else {  // (its A fragments are zero past lane 15 too)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          b[j] = s_b[(STEPS - 1) * 256 + j * 16 + (lane & 15)];
+          if (lane >= 16) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[j][e] = _Float16(0.0f);
+          }
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 4 * wave + r;
@@ -273,35 +338,37 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_block(
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b[j], acc[r][j], 0, 0, 0);
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(b[j], a, acc[r][j], 0, 0, 0);
       }
     }
-    // ---- epilogue: lane holds texels (row, 4 grp + i) of outputs 16 j + col
-    _Float16 hv[4][2][4];
+    // ---- epilogue: lane holds outputs 16 j + 4 grp + i (features j = 0, 1; gates j + 2) of
+    // texel (row, col): four consecutive channels, read and written as 8-byte pieces
+    half4 hv[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 4 * wave + r;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int c = 16 * j + col;
+        half4 up;
+        if (COARSE)
+          up = *reinterpret_cast<const half4*>(s_in + ((row + 1) * HALO + col + 1) * PSTRIDE +
+                                               16 * j + 4 * grp);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int x = 4 * grp + i;
           float v = elu_f(acc[r][j][i]) * sigmoid_f(acc[r][j + 2][i]);
-          if (COARSE) v += float(s_in[((row + 1) * HALO + x + 1) * PSTRIDE + c]);
+          if (COARSE) v += float(up[i]);
           hv[r][j][i] = _Float16(v);
         }
       }
     }
     __syncthreads();  // every wave is done with the halo; it becomes the output staging
-    _Float16* s_out = s_in;  // [256 texels][32]
+    _Float16* s_out = s_in;  // [256 texels][OSTRIDE]: texels 80 bytes apart hit other banks
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          s_out[((4 * wave + r) * TILE + 4 * grp + i) * FEAT + 16 * j + col] = hv[r][j][i];
+        *reinterpret_cast<half4*>(s_out + ((4 * wave + r) * TILE + col) * OSTRIDE + 16 * j +
+                                  4 * grp) = hv[r][j];
     __syncthreads();
     if (!FINAL) {  // 16-byte pieces: four per texel, tile rows contiguous in memory
       for (int u = t; u < TILE * TILE * 4; u += DEC_THREADS) {
@@ -309,19 +376,30 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_block(
         const int y = y0 + p / TILE, x = x0 + p % TILE;
         if (y < H && x < W)
           reinterpret_cast<uint4*>(hout)[(size_t(y) * W + x) * 4 + g] =
-              reinterpret_cast<const uint4*>(s_out)[p * 4 + g];
+              *reinterpret_cast<const uint4*>(s_out + p * OSTRIDE + 8 * g);
       }
-    } else {  // the output layer, one texel per thread
+    } else {  // the output layer, one texel per thread (weights from LDS, FO-padded)
       const int y = y0 + t / TILE, x = x0 + t % TILE;
       if (y < H && x < W) {
-        float o[MAX_OUT];
-        for (int k = 0; k < out_dim; ++k) o[k] = outw[FEAT * out_dim + k];
-        for (int c = 0; c < FEAT; ++c) {
-          const float h = float(s_out[t * FEAT + c]);
-          for (int k = 0; k < out_dim; ++k) o[k] = fmaf(h, outw[c * out_dim + k], o[k]);
+        float o[FINAL ? FO : 1];
+#pragma unroll
+        for (int k = 0; k < FO; ++k) o[k] = s_ow[FEAT * FO + k];
+        const half8* hp = reinterpret_cast<const half8*>(s_out + t * OSTRIDE);
+        constexpr int CU = FO == 3 ? FEAT / 8 : 1;  // (the generic width stays rolled)
+#pragma unroll CU
+        for (int c8 = 0; c8 < FEAT / 8; ++c8) {
+          const half8 hv8 = hp[c8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float h = float(hv8[e]);
+#pragma unroll
+            for (int k = 0; k < FO; ++k) o[k] = fmaf(h, s_ow[(8 * c8 + e) * FO + k], o[k]);
+          }
         }
         float* dst = image + (size_t(y) * W + x) * out_dim;
-        for (int k = 0; k < out_dim; ++k) dst[k] = o[k];
+#pragma unroll
+        for (int k = 0; k < FO; ++k)
+          if (k < out_dim) dst[k] = o[k];
       }
     }
   }
@@ -335,11 +413,14 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_block(
 
 bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Workgroups of one block launch: every tile once, at most a few per CU resident
-// (each holds the layer's packed kernel in LDS for all its tiles).
+// Workgroups of one block launch: one per tile up to two per CU (the residency the kernel's
+// LDS allows), each looping over tiles with the layer's packed kernel staged once.
 uint32_t dec_grid(int W, int H) {
   const uint32_t tiles = uint32_t((W + TILE - 1) / TILE) * uint32_t((H + TILE - 1) / TILE);
-  return std::min<uint32_t>(tiles, 256u * 4u);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return std::min<uint32_t>(tiles, 2u * uint32_t(std::max(cus, 1)));
 }
 
 template <int D>
@@ -352,21 +433,20 @@ trips_status launch_block(const DecLayout& d, const char* packed, int L, const f
   const int W = d.W[L], H = d.H[L];
   const int Wc = has_coarse ? d.W[L + 1] : 1, Hc = has_coarse ? d.H[L + 1] : 1;
   const dim3 grid(dec_grid(W, H)), blk(DEC_THREADS);
+  const int fo = image ? (d.out_dim == 3 ? 3 : MAX_OUT) : 0;
+#define DEC_LAUNCH(C, F)                                                                   \
+  hipLaunchKernelGGL((k_dec_block<D, C, F>), grid, blk, 0, st, feat, coarse, pk, ow, W, H, \
+                     Wc, Hc, d.out_dim, hout, image)
   if (has_coarse) {
-    if (image)
-      hipLaunchKernelGGL((k_dec_block<D, true, true>), grid, blk, 0, st, feat, coarse, pk, ow,
-                         W, H, Wc, Hc, d.out_dim, hout, image);
-    else
-      hipLaunchKernelGGL((k_dec_block<D, true, false>), grid, blk, 0, st, feat, coarse, pk, ow,
-                         W, H, Wc, Hc, d.out_dim, hout, image);
+    if (fo == 3) DEC_LAUNCH(true, 3);
+    else if (fo) DEC_LAUNCH(true, MAX_OUT);
+    else DEC_LAUNCH(true, 0);
   } else {
-    if (image)
-      hipLaunchKernelGGL((k_dec_block<D, false, true>), grid, blk, 0, st, feat, coarse, pk, ow,
-                         W, H, Wc, Hc, d.out_dim, hout, image);
-    else
-      hipLaunchKernelGGL((k_dec_block<D, false, false>), grid, blk, 0, st, feat, coarse, pk,
-                         ow, W, H, Wc, Hc, d.out_dim, hout, image);
+    if (fo == 3) DEC_LAUNCH(false, 3);
+    else if (fo) DEC_LAUNCH(false, MAX_OUT);
+    else DEC_LAUNCH(false, 0);
   }
+#undef DEC_LAUNCH
   DEC_HIP(hipGetLastError());
   return TRIPS_OK;
 }

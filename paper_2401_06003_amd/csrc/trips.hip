@@ -2117,9 +2117,12 @@ struct BlendedSrc {
   uint32_t pb;
   int pt;
 };
+// REBUILT is known at compile time, so every slot is one unconditional load from a selected
+// address (a load under a branch would wait on its own).
+template <bool REBUILT>
 __device__ __forceinline__ void blended_slot(const BlendedSrc& S, uint32_t b, int t, uint32_t fc,
                                              int m, uint64_t& key, float& gam) {
-  if (!S.kkey) {
+  if (!REBUILT) {
     const size_t o = (size_t(b) * KEEP + m) * TP + t;
     key = S.fkey[o];
     gam = S.fgam[o];
@@ -2130,15 +2133,17 @@ __device__ __forceinline__ void blended_slot(const BlendedSrc& S, uint32_t b, in
   const bool up = (mask >> m) & 1u;
   const size_t o = up ? (size_t(S.pb) * KEEP + ip) * TP + S.pt
                       : (size_t(b) * KEEP + (uint32_t(m) - ip)) * TP + t;
-  key = up ? S.fkey[o] : S.kkey[o];
-  gam = up ? S.fgam[o] : S.kgam[o];
+  const uint64_t* kp = up ? S.fkey : S.kkey;
+  const float* gp = up ? S.fgam : S.kgam;
+  key = kp[o];
+  gam = gp[o];
 }
 
 // Blend adjoint of the blended list of one texel (tile b, slot t, pyramid texel tex; fc its
 // count word): G, and per item m < k dg[m] = dL/dgamma_m and tg[m] = T_m gamma_m (zero past
 // k); writes the background gradient.  Returns k.  has_points: the cloud is not empty (an
 // empty slot then reads point 0's descriptor, which exists).
-template <int D>
+template <int D, bool REBUILT>
 __device__ __forceinline__ uint32_t blended_adjoint(const BlendedSrc& S, uint32_t b,
                                                     int t, uint32_t fc, size_t tex, bool has_points,
                                                     const float* __restrict__ desc,
@@ -2160,7 +2165,7 @@ __device__ __forceinline__ uint32_t blended_adjoint(const BlendedSrc& S, uint32_
   for (int m = 0; m < KEEP; ++m) {  // every slot is read (in bounds), those past k dropped
     uint64_t kr;
     float gr;
-    blended_slot(S, b, t, fc, m, kr, gr);
+    blended_slot<REBUILT>(S, b, t, fc, m, kr, gr);
     const bool ok = uint32_t(m) < k;
     idx[m] = ok ? uint32_t(kr) : 0u;
     gam[m] = ok ? gr : 0.0f;
@@ -2241,7 +2246,7 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   const size_t tex = size_t(c.lout[L]) + size_t(j) * WL + i;
   float G[D], dg[KEEP], tg[KEEP];
   const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
-  const uint32_t k = blended_adjoint<D>(src, b, t, fc, tex, P.n > 0, desc, gpyr, X, G, dg, tg);
+  const uint32_t k = blended_adjoint<D, false>(src, b, t, fc, tex, P.n > 0, desc, gpyr, X, G, dg, tg);
   // the finer texels this texel covers, and how many of its items each of them took
   size_t cbase[4];
   uint32_t cup[4];
@@ -2310,7 +2315,7 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
 // memory; layer Lt passes its coarser items up through memory (iup).
 constexpr int GROUP_PARENTS = 64 + 16 + 4 + 1;  // texels of the layers above a 16x16 tile
 template <int D>
-__global__ __launch_bounds__(256) void k_incl_bwd_group(
+__global__ __launch_bounds__(256, 1) void k_incl_bwd_group(
     const Params P, int Lb, int Lt, const uint64_t* __restrict__ fkey,
     const float* __restrict__ fgam, const uint32_t* __restrict__ fcnt,
     const float* __restrict__ desc, const float* __restrict__ gpyr, float* __restrict__ itot,
@@ -2326,43 +2331,47 @@ __global__ __launch_bounds__(256) void k_incl_bwd_group(
   const int tiles_x = (layer_dim(c.W, Lb) + (1 << ltw) - 1) >> ltw;
   const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
   const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
-  // block k's first slot in s_tot (layer Lb + k, k >= 1)
+  // block k's first slot in s_tot (layer Lb + k, k >= 1): blocks of 64, 16, 4 and 1 texels
   auto slot0 = [](int k) { int o = 0; for (int q = 1; q < k; ++q) o += TP >> (2 * q); return o; };
-  // the texel of this workgroup's block of layer Lb + k handled by thread t (false: none)
-  auto texel_of = [&](int k, int& i, int& j, int& WL, int& HL) {
+  // texel q of this workgroup's block of layer Lb + k (false: outside the block or the layer)
+  auto texel_at = [&](int k, int q, int& i, int& j, int& WL, int& HL) {
     const int rw = (1 << ltw) >> k, rh = (1 << lth) >> k;
-    if (t >= rw * rh) return false;
-    i = tx * rw + t % rw;
-    j = ty * rh + t / rw;
+    if (q >= rw * rh) return false;
+    i = tx * rw + q % rw;
+    j = ty * rh + q / rw;
     WL = layer_dim(c.W, Lb + k);
     HL = layer_dim(c.H, Lb + k);
     return i < WL && j < HL;
   };
-  // own parts of the layers above Lb
-  for (int k = 1; k <= Lt - Lb; ++k) {
+  auto texel_of = [&](int k, int& i, int& j, int& WL, int& HL) {
+    return texel_at(k, t, i, j, WL, HL);
+  };
+  // own parts of the layers above Lb, all at once: thread t takes slot t of s_tot (block k
+  // of the slot, texel t - slot0(k) of it)
+  if (t < slot0(Lt - Lb + 1)) {
+    int k = 1;
+    while (k < Lt - Lb && t >= slot0(k + 1)) ++k;
     int i, j, WL, HL;
-    const bool in = texel_of(k, i, j, WL, HL);
-    if (t < (TP >> (2 * k))) {
-      float (*tot)[S] = s_tot[slot0(k) + t];
-      float G[D], dg[KEEP], tg[KEEP];
+    const bool in = texel_at(k, t - slot0(k), i, j, WL, HL);
+    float (*tot)[S] = s_tot[t];
+    float G[D], dg[KEEP], tg[KEEP];
 #pragma unroll
-      for (int d = 0; d < D; ++d) G[d] = 0.0f;
+    for (int d = 0; d < D; ++d) G[d] = 0.0f;
 #pragma unroll
-      for (int m = 0; m < KEEP; ++m) { dg[m] = 0.0f; tg[m] = 0.0f; }
-      if (in) {
-        uint32_t b;
-        int tt;
-        texel_bin(P, v, Lb + k, i, j, b, tt);
-        const uint32_t fc = fcnt[size_t(b) * TP + tt];
-        blended_adjoint<D>(src, b, tt, fc, size_t(c.lout[Lb + k]) + size_t(j) * WL + i, P.n > 0,
-                           desc, gpyr, X, G, dg, tg);
-      }
+    for (int m = 0; m < KEEP; ++m) { dg[m] = 0.0f; tg[m] = 0.0f; }
+    if (in) {
+      uint32_t b;
+      int tt;
+      texel_bin(P, v, Lb + k, i, j, b, tt);
+      const uint32_t fc = fcnt[size_t(b) * TP + tt];
+      blended_adjoint<D, false>(src, b, tt, fc, size_t(c.lout[Lb + k]) + size_t(j) * WL + i, P.n > 0,
+                         desc, gpyr, X, G, dg, tg);
+    }
 #pragma unroll
-      for (int m = 0; m < KEEP; ++m) {
-        tot[m][0] = dg[m];
+    for (int m = 0; m < KEEP; ++m) {
+      tot[m][0] = dg[m];
 #pragma unroll
-        for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
-      }
+      for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
     }
   }
   __syncthreads();
@@ -2380,7 +2389,7 @@ __global__ __launch_bounds__(256) void k_incl_bwd_group(
       kk = (fc & 31u) + ((fc >> 5) & 31u);
       if (k == 0) {  // own part, then what layer L - 1 passed up (memory, an earlier launch)
         float G[D], dg[KEEP], tg[KEEP];
-        blended_adjoint<D>(src, b, tt, fc, size_t(c.lout[L]) + size_t(j) * WL + i, P.n > 0, desc,
+        blended_adjoint<D, false>(src, b, tt, fc, size_t(c.lout[L]) + size_t(j) * WL + i, P.n > 0, desc,
                            gpyr, X, G, dg, tg);
 #pragma unroll
         for (int m = 0; m < KEEP; ++m) {
@@ -2388,23 +2397,32 @@ __global__ __launch_bounds__(256) void k_incl_bwd_group(
 #pragma unroll
           for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
         }
-#pragma unroll 1
+        // the four finer texels (a missing one reads tile 0 and takes nothing), then their
+        // rows, every load issued whatever it is used for
+        size_t cbase[4];
+        uint32_t cup[4];
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int ci = 2 * i + (q & 1), cj = 2 * j + (q >> 1);
-          if (!(ci < layer_dim(c.W, L - 1) && cj < layer_dim(c.H, L - 1))) continue;
-          uint32_t cb;
-          int ct;
-          texel_bin(P, v, L - 1, ci, cj, cb, ct);
-          const uint32_t cup = (fcnt[size_t(cb) * TP + ct] >> 5) & 31u;
-          const size_t cbase = size_t(cb) * KEEP * S * TP + size_t(ct);
+          const bool cin = ci < layer_dim(c.W, L - 1) && cj < layer_dim(c.H, L - 1);
+          uint32_t cb = 0;
+          int ct = 0;
+          if (cin) texel_bin(P, v, L - 1, ci, cj, cb, ct);
+          cup[q] = cin ? (fcnt[size_t(cb) * TP + ct] >> 5) & 31u : 0u;
+          cbase[q] = size_t(cb) * KEEP * S * TP + size_t(ct);
+        }
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {  // one finer texel's rows in flight at a time
+          float u[KEEP][S];
+#pragma unroll
+          for (int m = 0; m < KEEP; ++m)
+#pragma unroll
+            for (int r = 0; r < S; ++r) u[m][r] = iup[cbase[q] + (size_t(m) * S + r) * TP];
 #pragma unroll
           for (int m = 0; m < KEEP; ++m) {
-            const bool take = uint32_t(m) < cup;
+            const bool take = uint32_t(m) < cup[q];
 #pragma unroll
-            for (int r = 0; r < S; ++r) {
-              const float u = iup[cbase + (size_t(m) * S + r) * TP];
-              tot[m][r] += take ? u : 0.0f;
-            }
+            for (int r = 0; r < S; ++r) tot[m][r] += take ? u[m][r] : 0.0f;
           }
         }
       } else {  // own part and every child's, already summed in LDS
@@ -2499,7 +2517,7 @@ __global__ __launch_bounds__(256) void k_incl_bwd01(
   {
     float G[D], dg[KEEP], tg[KEEP];
     const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
-    k = blended_adjoint<D>(src, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, P.n > 0,
+    k = blended_adjoint<D, false>(src, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, P.n > 0,
                            desc, gpyr, X, G, dg, tg);
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) {
@@ -2520,7 +2538,7 @@ __global__ __launch_bounds__(256) void k_incl_bwd01(
     float G[D], dg[KEEP], tg[KEEP];
     // layer 0's lists are rebuilt from their own lists and this texel's (b, t)
     const BlendedSrc csrc{fkey, fgam, kkey, kgam, b, t};
-    const uint32_t ck = blended_adjoint<D>(csrc, cb, ct, cfc,
+    const uint32_t ck = blended_adjoint<D, true>(csrc, cb, ct, cfc,
                                            size_t(c.lout[0]) + size_t(cj) * W0 + ci, P.n > 0, desc,
                                            gpyr, X, G, dg, tg);
     const size_t ctb = size_t(cb) * KEEP;
