@@ -245,31 +245,49 @@ __global__ __launch_bounds__(DEC_THREADS, 2) void k_dec_block(
       }
     }
     __syncthreads();
-    // ---- halo, phase 2: the doubled features of the 324 halo texels, from LDS
-    for (int u = t; u < HPIX * 4; u += DEC_THREADS) {
-      const int p = u >> 2, g = u & 3;
-      const int y = y0 + p / HALO - 1, x = x0 + p % HALO - 1;
-      half8 hv;
+    // ---- halo, phase 2 (below the coarsest layer only; the coarsest reads no doubled
+    // features): the doubled features from LDS, two halo rows by two halo columns per unit.
+    // Unit (ur, uc) covers layer rows 2k and 2k + 1 (halo rows 2 ur - 1, 2 ur), k = y0/2 - 1 +
+    // ur = cy0 + ur, and likewise columns: it reads the 3x3 staged coarser texels around
+    // (ur, uc) once and forms its four texels exactly as the per-texel formula (rows first at
+    // the near and the far column, each 3/4 near + 1/4 far, then columns).  Staged slots
+    // outside the region (clamped) only feed halo texels outside the halo, which are skipped.
+    if (COARSE) {
+      for (int u = t; u < CREG * CREG * 4; u += DEC_THREADS) {
+        const int g = u & 3, q = u >> 2, ur = q / CREG, uc = q % CREG;
+        half8 cr[3][3];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) hv[e] = _Float16(0.0f);
-      if (COARSE && y >= 0 && y < H && x >= 0 && x < W) {
-        int ny, fy, nx, fx;
-        up_taps(y, Hc, ny, fy);
-        up_taps(x, Wc, nx, fx);
-        ny -= cy0; fy -= cy0; nx -= cx0; fx -= cx0;  // inside the staged region
-        const half8 a = s_c[(ny * CREG + nx) * 4 + g];  // (near y, near x)
-        const half8 b = s_c[(fy * CREG + nx) * 4 + g];  // (far y, near x)
-        const half8 c = s_c[(ny * CREG + fx) * 4 + g];  // (near y, far x)
-        const half8 d = s_c[(fy * CREG + fx) * 4 + g];  // (far y, far x)
+        for (int a2 = 0; a2 < 3; ++a2)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          // rows first, then columns, each 3/4 near + 1/4 far
-          const float cn = fmaf(0.75f, float(a[e]), 0.25f * float(b[e]));
-          const float cf = fmaf(0.75f, float(c[e]), 0.25f * float(d[e]));
-          hv[e] = _Float16(fmaf(0.75f, cn, 0.25f * cf));
+          for (int b2 = 0; b2 < 3; ++b2) {
+            const int ry = min(max(ur - 1 + a2, 0), CREG - 1);
+            const int rx = min(max(uc - 1 + b2, 0), CREG - 1);
+            cr[a2][b2] = s_c[(ry * CREG + rx) * 4 + g];
+          }
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          // even layer row (dy = 0): far row above; odd (dy = 1): far row below
+          float v[3][8];
+#pragma unroll
+          for (int b2 = 0; b2 < 3; ++b2)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              v[b2][e] = fmaf(0.75f, float(cr[1][b2][e]), 0.25f * float(cr[dy ? 2 : 0][b2][e]));
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int hy = 2 * ur - 1 + dy, hx = 2 * uc - 1 + dx;
+            if (hy < 0 || hy >= HALO || hx < 0 || hx >= HALO) continue;
+            const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+            half8 hv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              hv[e] = (y >= 0 && y < H && x >= 0 && x < W)
+                          ? _Float16(fmaf(0.75f, v[1][e], 0.25f * v[dx ? 2 : 0][e]))
+                          : _Float16(0.0f);
+            reinterpret_cast<half8*>(s_in + (hy * HALO + hx) * PSTRIDE)[g] = hv;
+          }
         }
       }
-      reinterpret_cast<half8*>(s_in + p * PSTRIDE)[g] = hv;
     }
     __syncthreads();
     if (tile + int(gridDim.x) < tiles) fetch(tile + gridDim.x);  // in flight during the MFMAs

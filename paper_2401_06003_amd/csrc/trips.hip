@@ -3140,13 +3140,13 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     uint64_t* fkey = reinterpret_cast<uint64_t*>(sv + lay.s_fkey);
     float* fgam = reinterpret_cast<float*>(sv + lay.s_fgam);
     uint32_t* fcnt = reinterpret_cast<uint32_t*>(sv + lay.s_fcnt);
-    // layers 3 and up in groups of up to 1 + log2(shorter tile side) layers, coarsest group
-    // first, each one launch over the tiles of its finest layer; layers 0-2 (nearly all of
-    // the texels) keep one launch each
-    const int gmax = 1 + std::min(P.ltw, 8 - P.ltw);
+    // layers 2 and up in groups of up to 1 + log2(shorter tile side) layers counted from
+    // layer 2, coarsest group first, each one launch over the tiles of its finest layer;
+    // layers 0 and 1 (most of the texels) keep one launch each
+    const int gmax = std::min(1 + std::min(P.ltw, 8 - P.ltw), 5);
     int L = P.nl - 1;
-    while (L >= 3) {
-      const int Lb = std::max(3, L - gmax + 1);
+    while (L >= 2) {
+      const int Lb = 2 + ((L - 2) / gmax) * gmax;  // the group's finest layer
       hipLaunchKernelGGL(k_incl_fwd_group<D>, dim3(layer_tiles_max(P, Lb), uint32_t(P.V)),
                          dim3(256), 0, st, P, Lb, L, npix, kkey, kgam, fkey, fgam, fcnt,
                          pts.desc, pyr, X.bg, X.alpha);
@@ -3197,8 +3197,10 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
                            0, st, P, fkey, fgam, kkey, kgam, fcnt, pts.desc, gpyr, itot, iup, X);
         TRIPS_HIP(hipGetLastError());
       }
-      // layers 2 and below (when not fused) one launch each; from layer 3 on, groups of up to
-      // 1 + log2(shorter tile side) layers as one launch over their finest layer's tiles
+      // layers 2 and below (when not fused) one launch each (layer 2's per-layer pass reads
+      // the finer texels' rows faster than a group's first layer: 74 against about 150 us for a
+      // group of layers 2-6); from layer 3 on, groups of up to 1 + log2(shorter tile side)
+      // layers as one launch over their finest layer's tiles
       const int gmax = std::min(1 + std::min(P.ltw, 8 - P.ltw), 5);
       for (int L = fuse ? 2 : 0; L < P.nl;) {
         if (L < 3) {
