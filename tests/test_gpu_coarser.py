@@ -86,6 +86,21 @@ def test_small_scenes(gpu, seed, tile_w):
     assert (f["ids"][:, -1] >= 0).sum() > 0
 
 
+@pytest.mark.parametrize("tile_w", [8, 32])
+def test_eight_layers_grouped_passes(gpu, tile_w):
+    """Eight layers with tiles 8 texels on one side: the coarse layers run as groups of up to
+    four layers per launch (2-5 and 6-7 forward, 3-6 and 7 backward)."""
+    import paper_2401_06003_amd as tp
+    sc = scenes.random_small(520 + tile_w, n=3000, W=300, H=170, nlayers=8, s_lo=0.3,
+                             s_hi=200.0)
+    cam = sc["cams"][0]
+    P = oracle.num_pixels(cam["W"], cam["H"], sc["nlayers"])
+    bg, G, Ga = _inputs(P, sc["D"], 150 + tile_w)
+    got = _gpu(sc, gpu, bg, G, Ga, tp.make_tuning(tile_w, 0, 0))
+    got["gcam"] = got["gcam"][0]
+    _check_view(got, sc, cam, bg, G, Ga, where="8 layers, tile width %d " % tile_w)
+
+
 def test_depth_ties_and_single_layer(gpu):
     """Equal depths across points (index ties) and a point meeting itself across layers;
     with one layer inclusion changes nothing."""
