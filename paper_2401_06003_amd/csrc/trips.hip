@@ -1857,10 +1857,11 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
     const uint32_t kp = (pc & 31u) + ((pc >> 5) & 31u);
     if (g == 0) s_pn[q] = kp;
 #pragma unroll
-    for (int r = 0; r < KEEP / 4; ++r) {
+    for (int r = 0; r < KEEP / 4; ++r) {  // slots past kp read slot 0 again (a cache hit)
       const uint32_t m = uint32_t(g + 4 * r);
-      s_pk[m][q] = fkey[(size_t(pb) * KEEP + m) * TP + pt];
-      s_pg[m][q] = fgam[(size_t(pb) * KEEP + m) * TP + pt];
+      const size_t ms = m < kp ? m : 0u;
+      s_pk[m][q] = fkey[(size_t(pb) * KEEP + ms) * TP + pt];
+      s_pg[m][q] = fgam[(size_t(pb) * KEEP + ms) * TP + pt];
     }
   }
   __syncthreads();
@@ -1979,9 +1980,10 @@ __global__ __launch_bounds__(256) void k_incl_fwd_group(
         uint64_t ok[KEEP];
         float og[KEEP];
 #pragma unroll
-        for (int m = 0; m < KEEP; ++m) {  // every slot read (in bounds), those past ko unused
-          ok[m] = kkey[(tb + m) * TP + tt];
-          og[m] = kgam[(tb + m) * TP + tt];
+        for (int m = 0; m < KEEP; ++m) {  // every slot read (those past ko read slot 0 again, a
+          const size_t ms = uint32_t(m) < ko ? m : 0;  // cache hit) and left unused
+          ok[m] = kkey[(tb + ms) * TP + tt];
+          og[m] = kgam[(tb + ms) * TP + tt];
         }
         if (L == P.nl - 1) {  // the coarsest layer keeps its own lists (already blended)
 #pragma unroll
@@ -2008,9 +2010,10 @@ __global__ __launch_bounds__(256) void k_incl_fwd_group(
             const uint32_t pc = pin ? fcnt[size_t(pb) * TP + pt] : 0u;
             kp = (pc & 31u) + ((pc >> 5) & 31u);
 #pragma unroll
-            for (int m = 0; m < KEEP; ++m) {
-              pk[m] = fkey[(size_t(pb) * KEEP + m) * TP + pt];
-              pg[m] = fgam[(size_t(pb) * KEEP + m) * TP + pt];
+            for (int m = 0; m < KEEP; ++m) {  // (past kp: slot 0 again, unused)
+              const size_t ms = uint32_t(m) < kp ? m : 0;
+              pk[m] = fkey[(size_t(pb) * KEEP + ms) * TP + pt];
+              pg[m] = fgam[(size_t(pb) * KEEP + ms) * TP + pt];
             }
           } else {  // the block of layer L + 1 above, from LDS
             const int q = ((j >> 1) - ty * (rh >> 1)) * (rw >> 1) + ((i >> 1) - tx * (rw >> 1));
@@ -2162,10 +2165,10 @@ __device__ __forceinline__ uint32_t blended_adjoint(const BlendedSrc& S, uint32_
   float gam[KEEP], Tm[KEEP], gm[KEEP];
   uint32_t idx[KEEP];
 #pragma unroll
-  for (int m = 0; m < KEEP; ++m) {  // every slot is read (in bounds), those past k dropped
-    uint64_t kr;
+  for (int m = 0; m < KEEP; ++m) {  // every slot is read: those past k read slot 0 again (a
+    uint64_t kr;                    // cache hit, not a row of memory) and are dropped
     float gr;
-    blended_slot<REBUILT>(S, b, t, fc, m, kr, gr);
+    blended_slot<REBUILT>(S, b, t, fc, uint32_t(m) < k ? m : 0, kr, gr);
     const bool ok = uint32_t(m) < k;
     idx[m] = ok ? uint32_t(kr) : 0u;
     gam[m] = ok ? gr : 0.0f;
@@ -2211,13 +2214,17 @@ __device__ __forceinline__ uint32_t blended_adjoint(const BlendedSrc& S, uint32_
   return k;
 }
 
-// incl_bwd: one launch per layer, finest first; one workgroup per tile of the layer.  Per
-// texel the blend adjoint of its blended list (as bwd_pixels) gives every item
-// dL/dgamma and T gamma G; the four finer texels it covers add what their lists passed up
-// for the items they took from it.  Each item's total then goes to the own slot it came
-// from (itot, read by the rows of the entries) or, for items of the coarser list, up to
-// the covering texel (iup, read by the next launch).  Per slot the D + 1 values are
-// (dL/dgamma, dL/dtau contribution [D]), each row of 256 texels contiguous.
+// incl_bwd: one launch per layer, finest first; four threads per texel, a quarter of a tile
+// (64 texels) per workgroup (grid.x = 4 x the layer's tiles, grid.y = view).  All four
+// threads of a texel run the blend adjoint of its blended list (as bwd_pixels; their loads
+// are the same addresses, merged by the memory system), which gives every item dL/dgamma
+// and T gamma G; thread g then completes items g, g + 4, g + 8 and g + 12: the blend part,
+// then what each of the four finer texels the texel covers passed up for the item, in
+// child order.  Each item's total goes to the own slot it came from (itot, read by the rows
+// of the entries) or, for items of the coarser list, up to the covering texel (iup, read by
+// the next launch).  Per slot the D + 1 values are (dL/dgamma, dL/dtau contribution [D]),
+// each row of 256 texels contiguous.
+constexpr int INCL_LANES = 4;  // threads per texel in incl_bwd
 template <int D>
 __global__ __launch_bounds__(256) void k_incl_bwd(
     const Params P, int L, const uint64_t* __restrict__ fkey, const float* __restrict__ fgam,
@@ -2227,12 +2234,14 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   // iup_in and iup_out are the same table: this launch reads the rows of layer L - 1 and
   // writes those of layer L, which never overlap
   constexpr int S = D + 1;
+  constexpr int NH = KEEP / INCL_LANES;  // items per thread
   const int v = blockIdx.y;
   const ViewP& c = P.view[v];
-  const uint32_t local = blockIdx.x;
+  const uint32_t local = blockIdx.x / INCL_LANES;
   if (local >= c.lbin[L + 1] - c.lbin[L]) return;
   const uint32_t b = c.lbin[L] + local;
-  const int t = threadIdx.x;
+  const int g = threadIdx.x % INCL_LANES;
+  const int t = int(blockIdx.x % INCL_LANES) * (TP / INCL_LANES) + int(threadIdx.x) / INCL_LANES;
   const int lth = 8 - P.ltw;
   const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
   const int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
@@ -2244,9 +2253,6 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
   const uint32_t fc = fcnt[size_t(b) * TP + t];
   const uint32_t mask = fc >> 16;
   const size_t tex = size_t(c.lout[L]) + size_t(j) * WL + i;
-  float G[D], dg[KEEP], tg[KEEP];
-  const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
-  const uint32_t k = blended_adjoint<D, false>(src, b, t, fc, tex, P.n > 0, desc, gpyr, X, G, dg, tg);
   // the finer texels this texel covers, and how many of its items each of them took
   size_t cbase[4];
   uint32_t cup[4];
@@ -2264,42 +2270,56 @@ __global__ __launch_bounds__(256) void k_incl_bwd(
       }
     }
   }
-  // every item's total: its blend part, then what each finer texel passed up (in child
-  // order); all loads of a half list are issued before any store
-  uint32_t so = 0, sp = 0;
-  constexpr int H = D > 4 ? KEEP / 4 : KEEP / 2;
+  float tot[NH][S];
+  uint32_t k;
+  {
+    Extras Xg = X;  // the background gradient is written by one thread of the four
+    if (g != 0) Xg.gbg = nullptr;
+    float G[D], dg[KEEP], tg[KEEP];
+    const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
+    k = blended_adjoint<D, false>(src, b, t, fc, tex, P.n > 0, desc, gpyr, Xg, G, dg, tg);
+    // this thread's items, selected without indexing registers by g
 #pragma unroll
-  for (int h = 0; h < KEEP; h += H) {
-    float tot[H][S];
+    for (int h = 0; h < NH; ++h) {
+      const int m0 = INCL_LANES * h;
+      const float d0 = g == 0 ? dg[m0] : g == 1 ? dg[m0 + 1] : g == 2 ? dg[m0 + 2] : dg[m0 + 3];
+      const float t0 = g == 0 ? tg[m0] : g == 1 ? tg[m0 + 1] : g == 2 ? tg[m0 + 2] : tg[m0 + 3];
+      tot[h][0] = d0;
 #pragma unroll
-    for (int m = 0; m < H; ++m) {
-      tot[m][0] = dg[h + m];
+      for (int d = 0; d < D; ++d) tot[h][1 + d] = t0 * G[d];
+    }
+  }
+  // what each finer texel passed up, in child order; every row is read (in bounds: a
+  // missing child reads tile 0; an item the child did not take reads the child's slot 0,
+  // which the cache holds) and used only for the items that child took
 #pragma unroll
-      for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[h + m] * G[d];
+  for (int q = 0; q < 4; ++q) {
+    float u[NH][S];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const uint32_t m = uint32_t(INCL_LANES * h + g);
+      const size_t ms = m < cup[q] ? m : 0u;
+#pragma unroll
+      for (int r = 0; r < S; ++r) u[h][r] = iup_in[cbase[q] + (ms * S + r) * TP];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int h = 0; h < NH; ++h) {
+      const bool take = uint32_t(INCL_LANES * h + g) < cup[q];
 #pragma unroll
-      for (int m = 0; m < H; ++m) {
-        // read whatever the slot holds (in bounds: a missing child reads tile 0), use it
-        // only for the items that child took
-        const bool take = uint32_t(h + m) < cup[q];
+      for (int r = 0; r < S; ++r) tot[h][r] += take ? u[h][r] : 0.0f;
+    }
+  }
+  // item m of the list is the popc(mask below m)-th item taken from the coarser list, or
+  // the (m - that)-th own item
 #pragma unroll
-        for (int r = 0; r < S; ++r) {
-          const float u = iup_in[cbase[q] + (size_t(h + m) * S + r) * TP];
-          tot[m][r] += take ? u : 0.0f;
-        }
-      }
+  for (int h = 0; h < NH; ++h) {
+    const uint32_t m = uint32_t(INCL_LANES * h + g);
+    if (m < k) {
+      const bool up = (mask >> m) & 1u;
+      const uint32_t sp = __popc(mask & ((1u << m) - 1u)), so = m - sp;
+      float* dst = up ? iup_out + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
 #pragma unroll
-    for (int m = 0; m < H; ++m) {
-      if (uint32_t(h + m) < k) {
-        const bool up = (mask >> (h + m)) & 1u;
-        float* dst = up ? iup_out + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
-#pragma unroll
-        for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
-        sp += up ? 1u : 0u;
-        so += up ? 0u : 1u;
-      }
+      for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[h][r];
     }
   }
 }
@@ -2413,11 +2433,12 @@ __global__ __launch_bounds__(256, 1) void k_incl_bwd_group(
         }
 #pragma unroll 1
         for (int q = 0; q < 4; ++q) {  // one finer texel's rows in flight at a time
-          float u[KEEP][S];
+          float u[KEEP][S];  // (items the child did not take read its slot 0 again)
 #pragma unroll
           for (int m = 0; m < KEEP; ++m)
 #pragma unroll
-            for (int r = 0; r < S; ++r) u[m][r] = iup[cbase[q] + (size_t(m) * S + r) * TP];
+            for (int r = 0; r < S; ++r)
+              u[m][r] = iup[cbase[q] + (size_t(uint32_t(m) < cup[q] ? m : 0) * S + r) * TP];
 #pragma unroll
           for (int m = 0; m < KEEP; ++m) {
             const bool take = uint32_t(m) < cup[q];
@@ -2480,102 +2501,177 @@ __global__ __launch_bounds__(256, 1) void k_incl_bwd_group(
   }
 }
 
-// incl_bwd01: layers 0 and 1 in one launch, one workgroup per tile of layer 1.  Each thread
-// runs the blend adjoint of its layer-1 texel and then of the four layer-0 texels it covers,
-// whose items taken from it are added to its totals straight from registers (through a
-// per-thread LDS column), so layer 0 passes nothing up through memory.  Same totals and
-// summation order as two launches of incl_bwd.
+// incl_bwd012: layers 0, 1 and 2 in one launch, one workgroup per tile of layer 1 (the
+// texels of layer 2 over it form a (tw/2) x (th/2) block whose finer texels all lie in the
+// tile).  Each thread runs the blend adjoint of its layer-1 texel and then of the four
+// layer-0 texels it covers, whose items taken from it are added to its totals straight from
+// registers (through a per-thread LDS column), so layer 0 passes nothing up through memory;
+// then, one child position at a time, the layer-1 texels add their items of the coarser
+// list to the totals of their layer-2 texel in LDS, which start as that texel's own blend
+// part (computed first by the first PT threads); those threads finish layer 2, whose items
+// of the coarser list go up to layer 3 through memory (iup).  Same totals and summation
+// order as one launch of incl_bwd per layer.
 template <int D>
-__global__ __launch_bounds__(256) void k_incl_bwd01(
+__global__ __launch_bounds__(256) void k_incl_bwd012(
     const Params P, const uint64_t* __restrict__ fkey, const float* __restrict__ fgam,
     const uint64_t* __restrict__ kkey, const float* __restrict__ kgam,
     const uint32_t* __restrict__ fcnt, const float* __restrict__ desc,
-    const float* __restrict__ gpyr, float* __restrict__ itot, float* __restrict__ iup_out,
+    const float* __restrict__ gpyr, float* __restrict__ itot, float* __restrict__ iup,
     const Extras X) {
   constexpr int S = D + 1;
   __shared__ float s_dg[KEEP][TP];  // a child's items taken from this texel, in order
   __shared__ float s_tg[KEEP][TP];
+  __shared__ float s_up[PT][KEEP][S];  // totals of the block's layer-2 texels
   const int v = blockIdx.y;
   const ViewP& c = P.view[v];
   const uint32_t local = blockIdx.x;
-  if (local >= c.lbin[2] - c.lbin[1]) return;
+  if (local >= c.lbin[2] - c.lbin[1]) return;  // uniform per workgroup
   const uint32_t b = c.lbin[1] + local;
   const int t = threadIdx.x;
-  const int lth = 8 - P.ltw;
+  const int ltw = P.ltw, lth = 8 - P.ltw;
   const int W1 = layer_dim(c.W, 1), H1 = layer_dim(c.H, 1);
   const int W0 = layer_dim(c.W, 0), H0 = layer_dim(c.H, 0);
-  const int tiles_x = (W1 + (1 << P.ltw) - 1) >> P.ltw;
+  const int tiles_x = (W1 + (1 << ltw) - 1) >> ltw;
   const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
-  const int i = (tx << P.ltw) + (t & ((1 << P.ltw) - 1));
-  const int j = (ty << lth) + (t >> P.ltw);
-  if (!(i < W1 && j < H1)) return;  // (no barrier follows)
-  const size_t tb = size_t(b) * KEEP;
-  const uint32_t fc = fcnt[size_t(b) * TP + t];
-  const uint32_t mask = fc >> 16;
-  float tot[KEEP][S];
-  uint32_t k;
-  {
+  const int i = (tx << ltw) + (t & ((1 << ltw) - 1));
+  const int j = (ty << lth) + (t >> ltw);
+  const bool in = i < W1 && j < H1;
+  const bool two = P.nl > 2;  // uniform: layer 2 exists and is finished here
+  const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
+  // layer 2, own blend parts: thread t < PT takes texel t of the block
+  const int hw = 1 << (ltw - 1), hh = 1 << (lth - 1);
+  const int i2 = tx * hw + (t & (hw - 1)), j2 = ty * hh + (t >> (ltw - 1));
+  const int W2 = layer_dim(c.W, 2), H2 = layer_dim(c.H, 2);
+  const bool in2 = two && t < PT && i2 < W2 && j2 < H2;
+  uint32_t b2 = 0, fc2 = 0;
+  int t2 = 0;
+  if (two && t < PT) {
     float G[D], dg[KEEP], tg[KEEP];
-    const BlendedSrc src{fkey, fgam, nullptr, nullptr, 0u, 0};
-    k = blended_adjoint<D, false>(src, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, P.n > 0,
-                           desc, gpyr, X, G, dg, tg);
+#pragma unroll
+    for (int d = 0; d < D; ++d) G[d] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m) { dg[m] = 0.0f; tg[m] = 0.0f; }
+    if (in2) {
+      texel_bin(P, v, 2, i2, j2, b2, t2);
+      fc2 = fcnt[size_t(b2) * TP + t2];
+      blended_adjoint<D, false>(src, b2, t2, fc2, size_t(c.lout[2]) + size_t(j2) * W2 + i2,
+                                P.n > 0, desc, gpyr, X, G, dg, tg);
+    }
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) {
-      tot[m][0] = dg[m];
+      s_up[t][m][0] = dg[m];
 #pragma unroll
-      for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
+      for (int d = 0; d < D; ++d) s_up[t][m][1 + d] = tg[m] * G[d];
     }
   }
+  // layer 1 (and the four layer-0 texels of each of its texels)
+  const size_t tb = size_t(b) * KEEP;
+  uint32_t mask = 0, k = 0;
+  float tot[KEEP][S];
+  if (in) {
+    const uint32_t fc = fcnt[size_t(b) * TP + t];
+    mask = fc >> 16;
+    {
+      float G[D], dg[KEEP], tg[KEEP];
+      k = blended_adjoint<D, false>(src, b, t, fc, size_t(c.lout[1]) + size_t(j) * W1 + i, P.n > 0,
+                                    desc, gpyr, X, G, dg, tg);
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) {
+        tot[m][0] = dg[m];
+#pragma unroll
+        for (int d = 0; d < D; ++d) tot[m][1 + d] = tg[m] * G[d];
+      }
+    }
 #pragma unroll 1
-  for (int q = 0; q < 4; ++q) {
-    const int ci = 2 * i + (q & 1), cj = 2 * j + (q >> 1);
-    if (!(ci < W0 && cj < H0)) continue;
-    uint32_t cb;
-    int ct;
-    texel_bin(P, v, 0, ci, cj, cb, ct);
-    const uint32_t cfc = fcnt[size_t(cb) * TP + ct];
-    const uint32_t cmask = cfc >> 16;
-    float G[D], dg[KEEP], tg[KEEP];
-    // layer 0's lists are rebuilt from their own lists and this texel's (b, t)
-    const BlendedSrc csrc{fkey, fgam, kkey, kgam, b, t};
-    const uint32_t ck = blended_adjoint<D, true>(csrc, cb, ct, cfc,
-                                           size_t(c.lout[0]) + size_t(cj) * W0 + ci, P.n > 0, desc,
-                                           gpyr, X, G, dg, tg);
-    const size_t ctb = size_t(cb) * KEEP;
-    uint32_t so = 0, sp = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int ci = 2 * i + (q & 1), cj = 2 * j + (q >> 1);
+      if (!(ci < W0 && cj < H0)) continue;
+      uint32_t cb;
+      int ct;
+      texel_bin(P, v, 0, ci, cj, cb, ct);
+      const uint32_t cfc = fcnt[size_t(cb) * TP + ct];
+      const uint32_t cmask = cfc >> 16;
+      float G[D], dg[KEEP], tg[KEEP];
+      // layer 0's lists are rebuilt from their own lists and this texel's (b, t)
+      const BlendedSrc csrc{fkey, fgam, kkey, kgam, b, t};
+      const uint32_t ck = blended_adjoint<D, true>(csrc, cb, ct, cfc,
+                                                   size_t(c.lout[0]) + size_t(cj) * W0 + ci,
+                                                   P.n > 0, desc, gpyr, X, G, dg, tg);
+      const size_t ctb = size_t(cb) * KEEP;
+      uint32_t so = 0, sp = 0;
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m) {
+        if (uint32_t(m) < ck) {
+          if ((cmask >> m) & 1u) {
+            s_dg[sp][t] = dg[m];
+            s_tg[sp][t] = tg[m];
+            ++sp;
+          } else {
+            float* dst = itot + ((ctb + so) * S) * TP + ct;
+            dst[0] = dg[m];
+#pragma unroll
+            for (int d = 0; d < D; ++d) dst[size_t(1 + d) * TP] = tg[m] * G[d];
+            ++so;
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < KEEP; ++m)
+        if (uint32_t(m) < sp) {
+          tot[m][0] += s_dg[m][t];
+          const float w = s_tg[m][t];
+#pragma unroll
+          for (int d = 0; d < D; ++d) tot[m][1 + d] += w * G[d];
+        }
+    }
+    // own items to their slots
+    uint32_t so = 0;
 #pragma unroll
     for (int m = 0; m < KEEP; ++m) {
-      if (uint32_t(m) < ck) {
-        if ((cmask >> m) & 1u) {
-          s_dg[sp][t] = dg[m];
-          s_tg[sp][t] = tg[m];
-          ++sp;
-        } else {
-          float* dst = itot + ((ctb + so) * S) * TP + ct;
-          dst[0] = dg[m];
+      if (uint32_t(m) < k && !((mask >> m) & 1u)) {
+        float* dst = itot + ((tb + so) * S) * TP + t;
 #pragma unroll
-          for (int d = 0; d < D; ++d) dst[size_t(1 + d) * TP] = tg[m] * G[d];
-          ++so;
+        for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
+        ++so;
+      }
+    }
+  }
+  if (!two) return;  // uniform: layer 1 is the coarsest and takes nothing from above
+  // items of the coarser list to the layer-2 totals, one child position at a time
+  {
+    const int il = t & ((1 << ltw) - 1), jl = t >> ltw;
+    const int q = (jl & 1) * 2 + (il & 1);
+    const int pq = (jl >> 1) * hw + (il >> 1);
+#pragma unroll 1
+    for (int qd = 0; qd < 4; ++qd) {
+      __syncthreads();
+      if (in && q == qd) {
+        uint32_t sp = 0;
+#pragma unroll
+        for (int m = 0; m < KEEP; ++m) {
+          if (uint32_t(m) < k && ((mask >> m) & 1u)) {
+#pragma unroll
+            for (int r = 0; r < S; ++r) s_up[pq][sp][r] += tot[m][r];
+            ++sp;
+          }
         }
       }
     }
-#pragma unroll
-    for (int m = 0; m < KEEP; ++m)
-      if (uint32_t(m) < sp) {
-        tot[m][0] += s_dg[m][t];
-        const float w = s_tg[m][t];
-#pragma unroll
-        for (int d = 0; d < D; ++d) tot[m][1 + d] += w * G[d];
-      }
+    __syncthreads();
   }
+  if (!in2) return;
+  // layer 2: own items to their slots, items of the coarser list up to layer 3
+  const uint32_t mask2 = fc2 >> 16;
+  const uint32_t k2 = (fc2 & 31u) + ((fc2 >> 5) & 31u);
+  const size_t tb2 = size_t(b2) * KEEP;
   uint32_t so = 0, sp = 0;
 #pragma unroll
   for (int m = 0; m < KEEP; ++m) {
-    if (uint32_t(m) < k) {
-      const bool up = (mask >> m) & 1u;
-      float* dst = up ? iup_out + ((tb + sp) * S) * TP + t : itot + ((tb + so) * S) * TP + t;
+    if (uint32_t(m) < k2) {
+      const bool up = (mask2 >> m) & 1u;
+      float* dst = up ? iup + ((tb2 + sp) * S) * TP + t2 : itot + ((tb2 + so) * S) * TP + t2;
 #pragma unroll
-      for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = tot[m][r];
+      for (int r = 0; r < S; ++r) dst[size_t(r) * TP] = s_up[t][m][r];
       sp += up ? 1u : 0u;
       so += up ? 0u : 1u;
     }
@@ -3190,21 +3286,21 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     float* iup = reinterpret_cast<float*>(ws + lay.w_iup);
     {
       StageTimer tm(ST_INCL_BWD, st);
-      // the two finest layers run as one launch (layer 0 passes nothing up through memory)
+      // the three finest layers run as one launch (layers 0 and 1 pass nothing up through
+      // memory)
       const bool fuse = P.nl > 1;
       if (fuse) {
-        hipLaunchKernelGGL(k_incl_bwd01<D>, dim3(layer_tiles_max(P, 1), uint32_t(P.V)), dim3(256),
+        hipLaunchKernelGGL(k_incl_bwd012<D>, dim3(layer_tiles_max(P, 1), uint32_t(P.V)), dim3(256),
                            0, st, P, fkey, fgam, kkey, kgam, fcnt, pts.desc, gpyr, itot, iup, X);
         TRIPS_HIP(hipGetLastError());
       }
-      // layers 2 and below (when not fused) one launch each (layer 2's per-layer pass reads
-      // the finer texels' rows faster than a group's first layer: 74 against about 150 us for a
-      // group of layers 2-6); from layer 3 on, groups of up to 1 + log2(shorter tile side)
-      // layers as one launch over their finest layer's tiles
+      // a single layer on its own; from layer 3 on, groups of up to 1 + log2(shorter tile
+      // side) layers as one launch over their finest layer's tiles
       const int gmax = std::min(1 + std::min(P.ltw, 8 - P.ltw), 5);
-      for (int L = fuse ? 2 : 0; L < P.nl;) {
+      for (int L = fuse ? 3 : 0; L < P.nl;) {
         if (L < 3) {
-          hipLaunchKernelGGL(k_incl_bwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256),
+          hipLaunchKernelGGL(k_incl_bwd<D>, dim3(layer_tiles_max(P, L) * INCL_LANES, uint32_t(P.V)),
+                             dim3(256),
                              0, st, P, L, fkey, fgam, fcnt, pts.desc, gpyr, itot, iup, iup, X);
           ++L;
         } else {
