@@ -417,6 +417,11 @@ __device__ __forceinline__ TileCount tile_count(const uint32_t* __restrict__ tot
                                                 uint32_t NB, uint32_t item_e, uint32_t fine_e) {
   return tile_count_of(b < NB ? tot[b] : 0u, b < NB, item_e, fine_e);
 }
+// Size class of every item of a tile: the forward takes the items of a tile as strided
+// blocks of its entries, so they are of equal size (within a block), e / it on average.
+__device__ __forceinline__ uint32_t item_class(const TileCount& c, uint32_t item_e) {
+  return c.it ? size_class(ceil_div(c.e, c.it), item_e) : 0u;
+}
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
@@ -428,13 +433,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // fine tiles and the items per size class; lane 0 writes them.
 __device__ __forceinline__ void chunk_sums(const TileCount& c, uint32_t item_e,
                                            uint32_t* __restrict__ out) {
-  // it - 1 items of item_e entries (class 0) and a last one of the rest
-  const uint32_t cls = c.it ? size_class(c.e - (c.it - 1) * item_e, item_e) : 0u;
+  const uint32_t cls = item_class(c, item_e);  // (all items of a tile)
   uint32_t v[CSUM];
   v[0] = c.e; v[1] = c.it; v[2] = c.multi; v[3] = c.fine;
 #pragma unroll
-  for (int q = 0; q < NBUCKET; ++q)
-    v[4 + q] = (q == 0 && c.it ? c.it - 1 : 0u) + (c.it && cls == uint32_t(q) ? 1u : 0u);
+  for (int q = 0; q < NBUCKET; ++q) v[4 + q] = cls == uint32_t(q) ? c.it : 0u;
 #pragma unroll
   for (int q = 0; q < CSUM; ++q) {
     const uint32_t w = wave_sum_u32(v[q]);
@@ -664,13 +667,11 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
     if (c.fine) fine_work[of] = make_uint4(b, oe, oe + c.e, 0u);
     else coarse_bins[b - of] = b;  // tiles before b that are not fine
   }
-  // work items: all but the last hold item_e entries (class 0)
-  const uint32_t nfull = c.it ? c.it - 1 : 0u;
-  const uint32_t elast = oe + nfull * item_e;
-  const uint32_t q = size_class(oe + c.e - elast, item_e);
+  // work items: consecutive ranges of item_e entries (the last holds the rest), all in the
+  // class of the tile's average item (the forward takes them as strided blocks)
+  const uint32_t q = item_class(c, item_e);
   __syncthreads();
-  const uint32_t rf = nfull ? atomicAdd(&s_cnt[0], nfull) : 0u;
-  const uint32_t rl = c.it ? atomicAdd(&s_cnt[q], 1u) : 0u;
+  const uint32_t rf = c.it ? atomicAdd(&s_cnt[q], c.it) : 0u;
   __syncthreads();
   if (!FUSED && t < NBUCKET && s_cnt[t])
     s_base[t] = info[INFO_BUCKET + t] + atomicAdd(&info[INFO_BUCKET + NBUCKET + t], s_cnt[t]);
@@ -680,11 +681,10 @@ __global__ __launch_bounds__(64) void k_binscan(const uint32_t* __restrict__ tot
   // this one (oi counts one item for each of the b - om - of single-item tiles before it)
   const uint32_t multi = c.it > 1 ? 0x80000000u : 0u;
   const uint32_t pslot = multi ? oi - (b - om - of) : 0u;
-  for (uint32_t k = 0; k < nfull; ++k) {
+  for (uint32_t k = 0; k < c.it; ++k) {
     const uint32_t e0 = oe + k * item_e;
-    work[s_base[0] + rf + k] = make_uint4(b, e0, e0 + item_e, (pslot + k) | multi);
+    work[s_base[q] + rf + k] = make_uint4(b, e0, min(e0 + item_e, oe + c.e), (pslot + k) | multi);
   }
-  work[s_base[q] + rl] = make_uint4(b, elast, oe + c.e, (pslot + c.it - 1) | multi);
 }
 
 // scatter: the count pass again, with LDS ranks; entry -> bin_start + H (column prefix) + rank.
@@ -904,6 +904,8 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
 constexpr int EPT = 2;                // entries per thread per LDS round
 constexpr int SUB_E = EPT * TP;       // entries per LDS round
 constexpr int SUB_F = 4 * SUB_E;      // fragments per LDS round (at most 4 per entry)
+constexpr uint32_t ENT_BLK = 16;      // consecutive entries taken together by fwd_items
+constexpr uint32_t RND_BLK = SUB_E / ENT_BLK;  // blocks per round
 
 // Compare-exchange of (key, gamma) pairs: afterwards a holds the smaller key.
 __device__ __forceinline__ void cswap(uint64_t& ka, float& ga, uint64_t& kb, float& gb) {
@@ -934,6 +936,12 @@ __device__ __forceinline__ void merge16(uint64_t (&k)[KEEP], float (&g)[KEEP],
 // entries into fragments, counting-sorts them by texel and lets the thread owning the texel
 // insert them into its register top-16; in the first round, whose lists are all empty, the
 // fragments' depth ranks are counted in LDS instead and the first 16 ranks loaded in order.
+// The entries are taken in blocks of ENT_BLK consecutive ones, strided over the tile: item i
+// of a tile with I items takes blocks i, i + I, ..., and round r of an item with R rounds
+// its blocks r, r + R, ...  A round then mixes entries from the whole tile whatever the
+// order of the points (consecutive points of a spatially ordered cloud crowd a few texels,
+// whose threads would insert long runs while the others idle), and the loads stay
+// coalesced per block.  The result does not depend on the order.
 // A fragment whose depth bits are above those of the texel's current 16th key is only
 // counted, never sorted (the insertion makes the exact comparison).  A texel's tally and its
 // count of sorted fragments share one LDS word, so a fragment costs one LDS atomic.
@@ -944,6 +952,7 @@ static_assert(4u * SUB_E < (1u << (32 - TALLY_BITS)), "run starts fit the high b
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_items(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ work,
+    const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ item_start,
     const Entry* __restrict__ ent, const float* __restrict__ desc, float* __restrict__ pyr,
     uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam,
     uint32_t* __restrict__ pcnt, uint64_t* __restrict__ pkey, float* __restrict__ pgam,
@@ -962,9 +971,26 @@ __global__ __launch_bounds__(256) void k_fwd_items(
   const uint32_t total = info[1];
   const uint4 wk = work[blockIdx.x];  // in bounds (grid = capacity); used only if valid
   if (blockIdx.x >= total) return;
-  const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z, it = wk.w & 0x7fffffffu;
+  const uint32_t b = wk.x, it = wk.w & 0x7fffffffu;
   const bool multi = (wk.w >> 31) != 0;
   const BinInfo bi = decode_bin(P, b);
+  // the item's blocks (uniform): the tile's entries t0..t1, item ii of ni
+  uint32_t t0 = wk.y, t1 = wk.z, ni = 1, ii = 0;
+  if (multi) {
+    t0 = bin_start[b];
+    t1 = bin_start[b + 1];
+    ni = item_start[b + 1] - item_start[b];
+    ii = (wk.y - t0) / P.item_e;
+  }
+  const uint32_t nbt = (t1 - t0 + ENT_BLK - 1) / ENT_BLK;  // the tile's blocks (ii < ni <= nbt)
+  const uint32_t nbi = (nbt - ii + ni - 1) / ni;           // the item's
+  const uint32_t nr = (nbi + RND_BLK - 1) / RND_BLK;       // rounds
+  // position of entry slot s (0 .. SUB_E - 1) of round r, or t1 if the slot is empty
+  auto entry_at = [&](uint32_t r, uint32_t s) {
+    const uint32_t kb = r + nr * (s / ENT_BLK);
+    const uint32_t pos = t0 + (ii + ni * kb) * ENT_BLK + s % ENT_BLK;
+    return kb < nbi && pos < t1 ? pos : t1;
+  };
   uint64_t kk[KEEP];
   float kg[KEEP];
 #pragma unroll
@@ -973,10 +999,13 @@ __global__ __launch_bounds__(256) void k_fwd_items(
   thz[t] = ~0u;
   // entries of the current round, loaded one round ahead
   Entry en[EPT];
+  uint32_t ep[EPT];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q)
-    if (e0 + q * TP + t < e1) en[q] = ent[e0 + q * TP + t];
-  for (uint32_t s0 = e0; s0 < e1; s0 += SUB_E) {
+  for (int q = 0; q < EPT; ++q) {
+    ep[q] = entry_at(0, q * TP + t);
+    if (ep[q] < t1) en[q] = ent[ep[q]];
+  }
+  for (uint32_t r = 0; r < nr; ++r) {
     th[t] &= TALLY_MASK;
     __syncthreads();
     uint32_t cm[EPT], rank[EPT][2];  // corner masks; 16-bit ranks, two per word
@@ -985,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_fwd_items(
       cm[q] = 0;
       rank[q][0] = rank[q][1] = 0;
       Corner cs[4];
-      if (s0 + q * TP + t < e1) cm[q] = entry_corners(en[q], bi, P.ltw, cs);
+      if (ep[q] < t1) cm[q] = entry_corners(en[q], bi, P.ltw, cs);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if ((cm[q] >> c) & 1u) {
@@ -998,9 +1027,12 @@ __global__ __launch_bounds__(256) void k_fwd_items(
       }
     }
     Entry nx[EPT];  // next round's entries
+    uint32_t np[EPT];
 #pragma unroll
-    for (int q = 0; q < EPT; ++q)
-      if (s0 + SUB_E + q * TP + t < e1) nx[q] = ent[s0 + SUB_E + q * TP + t];
+    for (int q = 0; q < EPT; ++q) {
+      np[q] = r + 1 < nr ? entry_at(r + 1, q * TP + t) : t1;
+      if (np[q] < t1) nx[q] = ent[np[q]];
+    }
     __syncthreads();
     const uint32_t cnt = th[t] >> TALLY_BITS;
     uint32_t tot;
@@ -1024,7 +1056,7 @@ __global__ __launch_bounds__(256) void k_fwd_items(
         }
     }
     __syncthreads();
-    if (s0 == e0) {
+    if (r == 0) {
       // first round: every list is empty, so a texel's list is simply the first ranks of its
       // run.  Every fragment counts the smaller keys of its run (its depth rank; keys are
       // distinct in a texel), then each thread loads its first 16 ranks in order.
@@ -1069,7 +1101,7 @@ __global__ __launch_bounds__(256) void k_fwd_items(
     }
     thz[t] = uint32_t(kk[KEEP - 1] >> 32);
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) en[q] = nx[q];
+    for (int q = 0; q < EPT; ++q) { en[q] = nx[q]; ep[q] = np[q]; }
     __syncthreads();
   }
   const uint32_t n = th[t] & TALLY_MASK;
@@ -3205,8 +3237,8 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
        // item count exit at once
       StageTimer tm(ST_FWD_ITEMS, st);
       hipLaunchKernelGGL(k_fwd_items<D>, dim3(uint32_t(lay.icap)), dim3(256), 0, st, P, info,
-                         work, ent, pts.desc, pyr, npix, kkey, kgam, pcnt, pkey, pgam, X.bg,
-                         X.alpha);
+                         work, bin_start, item_start, ent, pts.desc, pyr, npix, kkey, kgam, pcnt,
+                         pkey, pgam, X.bg, X.alpha);
     }
     hipError_t e3 = hipGetLastError();
     hipError_t e0 = hipStreamWaitEvent(sd->s, sd->fork, 0);
