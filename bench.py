@@ -17,7 +17,8 @@ reported: per-kernel durations (eager steps with HIP events around every launch,
 stream); the roofline of the dominant kernel in the method's own byte units (per fragment,
 kept fragment, texel and point) beside the implementation's byte model; the whole step's
 fraction of HBM peak; a plain device copy's bandwidth; the forward alone at the same size;
-the 4096-point 256x256 forward latency; the reconstruction network (Sec. 3.3) on the rendered
+the 4096-point 256x256 forward latency; the same cloud in Morton order of position (a
+spatially coherent input order) instead of shuffled; the reconstruction network (Sec. 3.3) on the rendered
 pyramid, with its matrix-core roofline; the same workload with coarser-layer inclusion; the
 batched multi-view form (16 views of mixed resolution over 4M points, autotuned launch shape)
 against 16 single-view launch sequences; 8M points at 1080p; the optimisation loop (8M
@@ -384,6 +385,32 @@ def run_points_8m(torch, tp, scenes, steps, warmup, dev):
             "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()}}
 
 
+def run_ordered(torch, tp, scenes, sc, G, steps, warmup, dev):
+    """The headline cloud with its points in Morton order of position (a spatially coherent
+    cloud, as a scan or a reconstruction delivers it) instead of shuffled: same fragments and
+    results, a different order of the entries within every tile."""
+    so = scenes.morton_sorted(sc)
+    cam, nl, D = so["cams"][0], so["nlayers"], so["D"]
+    n = len(so["points"]["x"])
+    t = {k: torch.from_numpy(so["points"][k]).to(dev) for k in PARAMS}
+    args = [t[k] for k in PARAMS]
+    r = tp.Renderer([cam], nl, D, n, device=dev)
+    pyr = torch.empty(r.pyramid_numel(), device=dev)
+    grads = [torch.empty(n, device=dev) for _ in range(5)] + [torch.empty((n, D), device=dev)]
+
+    def step():
+        r.forward(*args, out=pyr)
+        r.backward(*args, G, outs=grads)
+
+    for _ in range(warmup):
+        step()
+    ms = timed(torch, step, steps)
+    stage_ms, _ = stage_times(torch, tp, step, steps)
+    return {"workload": "clusters2m_1920x1080_8layers_d4_fwd_bwd_morton_order", "points": n,
+            "ms_per_step": ms, "points_per_s": n / (ms / 1e3),
+            "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()}}
+
+
 def run_batched(torch, tp, scenes, steps, warmup, dev, cpu_views=0):
     """16 views of mixed resolution over 4M points.  The launch shape is picked by the
     autotuner (forward + backward of the whole batch timed per candidate); then one batched
@@ -743,6 +770,8 @@ def main():
                                                None if args.no_cpu_baseline else sc)
         log("4096 points at 256x256")
         out["small"] = run_small_latency(torch, tp, scenes, args.steps, dev)
+        log("the headline cloud in Morton order")
+        out["ordered_input"] = run_ordered(torch, tp, scenes, sc, G, args.steps, args.warmup, dev)
     if not args.no_decoder:
         log("reconstruction network on the rendered pyramid")
         r.forward(*pargs, out=pyr)

@@ -130,6 +130,24 @@ def cluster_scene(seed=2, n=2_000_000, W=1920, H=1080, nlayers=8, D=4, s_lo=0.5,
     return {"points": _points(xyz, sw, alpha, desc), "cams": [cam], "nlayers": nlayers, "D": D}
 
 
+def morton_sorted(sc, bits=10):
+    """The same scene with its points reordered along a Morton (Z-order) curve of their
+    positions, 3 x `bits` bits: the order of a spatially coherent cloud, where consecutive
+    points are neighbours in space and on screen."""
+    p = sc["points"]
+    xyz = np.stack([p["x"], p["y"], p["z"]], axis=1).astype(np.float64)
+    lo, hi = xyz.min(axis=0), xyz.max(axis=0)
+    q = ((xyz - lo) / np.maximum(hi - lo, 1e-30) * ((1 << bits) - 1)).astype(np.uint64)
+    code = np.zeros(len(xyz), dtype=np.uint64)
+    for b in range(bits):
+        for a in range(3):
+            code |= ((q[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + a)
+    order = np.argsort(code, kind="stable")
+    out = dict(sc)
+    out["points"] = {k: np.ascontiguousarray(v[order]) for k, v in p.items()}
+    return out
+
+
 def upstream_gradient(seed, n_values):
     """Upstream pyramid gradient, N(0, 1) float32."""
     return np.random.default_rng(seed).standard_normal(n_values).astype(np.float32)

@@ -92,6 +92,18 @@ def test_run_twice_bitwise(gpu):
         assert np.array_equal(a[0][k], b[0][k])
 
 
+@pytest.mark.parametrize("item", [512, 1024])
+def test_spatially_ordered_points(gpu, item):
+    """A cluster scene whose points are in Morton order (consecutive points crowd the same
+    texels): every list is compared, with work items small enough that heavy tiles are cut
+    into several, whose entries the forward takes as interleaved blocks."""
+    sc = scenes.morton_sorted(scenes.cluster_scene(5, n=120_000, W=480, H=270, nlayers=6,
+                                                   s_hi=64.0))
+    res, r, _ = check_forward(sc, gpu, _tune(16, 0, item))
+    entries, _ = r.tile_stats()
+    assert (entries > item).sum() > 4  # tiles cut into several items
+
+
 def test_cluster_scene_full_size_sampled(gpu):
     """2M points, 1920x1080, 8 layers: every texel's list and kept ids are compared on a
     sample of texels from every layer (the oracle evaluates only those texels)."""
