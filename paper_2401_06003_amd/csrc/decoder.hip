@@ -246,45 +246,51 @@ __global__ __launch_bounds__(DEC_THREADS, 2) void k_dec_block(
     }
     __syncthreads();
     // ---- halo, phase 2 (below the coarsest layer only; the coarsest reads no doubled
-    // features): the doubled features from LDS, two halo rows by two halo columns per unit.
-    // Unit (ur, uc) covers layer rows 2k and 2k + 1 (halo rows 2 ur - 1, 2 ur), k = y0/2 - 1 +
-    // ur = cy0 + ur, and likewise columns: it reads the 3x3 staged coarser texels around
-    // (ur, uc) once and forms its four texels exactly as the per-texel formula (rows first at
-    // the near and the far column, each 3/4 near + 1/4 far, then columns).  Staged slots
-    // outside the region (clamped) only feed halo texels outside the halo, which are skipped.
+    // features): the doubled features from LDS, two halo rows by four halo columns per unit.
+    // Unit (ur, uc2) covers layer rows 2k and 2k + 1 (halo rows 2 ur - 1, 2 ur), k = y0/2 - 1
+    // + ur = cy0 + ur, and the layer columns of the coarser columns 2 uc2 and 2 uc2 + 1 (halo
+    // columns 4 uc2 - 1 .. 4 uc2 + 2): it reads the 3x4 staged coarser texels around them once,
+    // blends each of the four coarser columns along the rows once, and forms its eight texels
+    // exactly as the per-texel formula (rows first at the near and the far column, each 3/4
+    // near + 1/4 far, then columns).  Staged slots outside the region (clamped) only feed halo
+    // texels outside the halo, which are skipped.
     if (COARSE) {
-      for (int u = t; u < CREG * CREG * 4; u += DEC_THREADS) {
-        const int g = u & 3, q = u >> 2, ur = q / CREG, uc = q % CREG;
-        half8 cr[3][3];
+      constexpr int CP = CREG / 2;  // column pairs
+      for (int u = t; u < CREG * CP * 4; u += DEC_THREADS) {
+        const int g = u & 3, q = u >> 2, ur = q / CP, uc2 = q % CP;
+        half8 cr[3][4];
 #pragma unroll
         for (int a2 = 0; a2 < 3; ++a2)
 #pragma unroll
-          for (int b2 = 0; b2 < 3; ++b2) {
+          for (int j = 0; j < 4; ++j) {
             const int ry = min(max(ur - 1 + a2, 0), CREG - 1);
-            const int rx = min(max(uc - 1 + b2, 0), CREG - 1);
-            cr[a2][b2] = s_c[(ry * CREG + rx) * 4 + g];
+            const int rx = min(max(2 * uc2 - 1 + j, 0), CREG - 1);
+            cr[a2][j] = s_c[(ry * CREG + rx) * 4 + g];
           }
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
           // even layer row (dy = 0): far row above; odd (dy = 1): far row below
-          float v[3][8];
+          float v[4][8];
 #pragma unroll
-          for (int b2 = 0; b2 < 3; ++b2)
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              v[b2][e] = fmaf(0.75f, float(cr[1][b2][e]), 0.25f * float(cr[dy ? 2 : 0][b2][e]));
-#pragma unroll
-          for (int dx = 0; dx < 2; ++dx) {
-            const int hy = 2 * ur - 1 + dy, hx = 2 * uc - 1 + dx;
-            if (hy < 0 || hy >= HALO || hx < 0 || hx >= HALO) continue;
-            const int y = y0 - 1 + hy, x = x0 - 1 + hx;
-            half8 hv;
+          for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-              hv[e] = (y >= 0 && y < H && x >= 0 && x < W)
-                          ? _Float16(fmaf(0.75f, v[1][e], 0.25f * v[dx ? 2 : 0][e]))
-                          : _Float16(0.0f);
-            reinterpret_cast<half8*>(s_in + (hy * HALO + hx) * PSTRIDE)[g] = hv;
+              v[j][e] = fmaf(0.75f, float(cr[1][j][e]), 0.25f * float(cr[dy ? 2 : 0][j][e]));
+#pragma unroll
+          for (int w = 0; w < 2; ++w) {  // coarser column 2 uc2 + w: near j = 1 + w
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {  // far column j = w (dx = 0) or 2 + w (dx = 1)
+              const int hy = 2 * ur - 1 + dy, hx = 2 * (2 * uc2 + w) - 1 + dx;
+              if (hy < 0 || hy >= HALO || hx < 0 || hx >= HALO) continue;
+              const int y = y0 - 1 + hy, x = x0 - 1 + hx;
+              const bool inimg = y >= 0 && y < H && x >= 0 && x < W;
+              half8 hv;
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                hv[e] = inimg ? _Float16(fmaf(0.75f, v[1 + w][e], 0.25f * v[dx ? 2 + w : w][e]))
+                              : _Float16(0.0f);
+              reinterpret_cast<half8*>(s_in + (hy * HALO + hx) * PSTRIDE)[g] = hv;
+            }
           }
         }
       }
