@@ -267,6 +267,10 @@ __global__ __launch_bounds__(DEC_THREADS, 2) void k_dec_block(
             const int rx = min(max(2 * uc2 - 1 + j, 0), CREG - 1);
             cr[a2][j] = s_c[(ry * CREG + rx) * 4 + g];
           }
+        // 3/4 near + 1/4 far is (3 near + far) / 4, and a power-of-two scale is exact: each
+        // pass forms 3 near + far with one rounding (from the binary16 values directly along
+        // the rows), and the doubled value is the column pass's result times 1/16, the same
+        // float32 as 3/4 near + 1/4 far taken twice, then rounded to binary16
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
           // even layer row (dy = 0): far row above; odd (dy = 1): far row below
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(DEC_THREADS, 2) void k_dec_block(
           for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-              v[j][e] = fmaf(0.75f, float(cr[1][j][e]), 0.25f * float(cr[dy ? 2 : 0][j][e]));
+              v[j][e] = fmaf(3.0f, float(cr[1][j][e]), float(cr[dy ? 2 : 0][j][e]));
 #pragma unroll
           for (int w = 0; w < 2; ++w) {  // coarser column 2 uc2 + w: near j = 1 + w
 #pragma unroll
@@ -287,9 +291,11 @@ __global__ __launch_bounds__(DEC_THREADS, 2) void k_dec_block(
               half8 hv;
 #pragma unroll
               for (int e = 0; e < 8; ++e)
-                hv[e] = inimg ? _Float16(fmaf(0.75f, v[1 + w][e], 0.25f * v[dx ? 2 + w : w][e]))
-                              : _Float16(0.0f);
-              reinterpret_cast<half8*>(s_in + (hy * HALO + hx) * PSTRIDE)[g] = hv;
+                hv[e] = _Float16(0.0625f * fmaf(3.0f, v[1 + w][e], v[dx ? 2 + w : w][e]));
+              uint4 hw = *reinterpret_cast<const uint4*>(&hv);
+              hw.x = inimg ? hw.x : 0u; hw.y = inimg ? hw.y : 0u;
+              hw.z = inimg ? hw.z : 0u; hw.w = inimg ? hw.w : 0u;
+              reinterpret_cast<uint4*>(s_in + (hy * HALO + hx) * PSTRIDE)[g] = hw;
             }
           }
         }
