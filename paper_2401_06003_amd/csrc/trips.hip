@@ -81,14 +81,13 @@ struct Params {
   ViewP view[MAXV];
 };
 
-struct __align__(8) Entry {
+struct __align__(4) Entry {
   uint32_t idx;    // point index
   uint32_t zbits;  // bits of the camera depth (positive float: order preserving)
   float u, v;      // layer-texel coordinates of the point, x / 2^L - 0.5
   float ia;        // iota * alpha
-  uint32_t slot;   // layer entry (0/1) * 4 + tile touch (0..3)
 };
-static_assert(sizeof(Entry) == 24, "entry layout");
+static_assert(sizeof(Entry) == 20, "entry layout");
 
 // ------------------------------------------------------------------------------------
 // Geometry shared by every kernel that needs a point's footprint.  Compiled without
@@ -762,7 +761,6 @@ __global__ __launch_bounds__(BIN_THREADS) void k_scatter(const Params P, const f
                      e.u = ft.u;
                      e.v = ft.v;
                      e.ia = g.io[sel] * alpha;
-                     e.slot = slot;
                      const uint32_t at = (STAGED ? base[lb] : bs[lb] + row[lb]) + rank;
                      ent[at] = e;
 #pragma unroll
@@ -1122,9 +1120,9 @@ __global__ __launch_bounds__(256) void k_fwd_items(
   }
 }
 
-// Entry.slot of an entry of a fine tile, once the forward pass ran: bits 0..2 are the row
-// slot, bits 8 + 5c .. 12 + 5c the kept slot (0..15) of corner c, 31 if absent or not kept.
-constexpr uint32_t KSLOT_SHIFT = 8;
+// Kept slots of the entries of a fine tile, once the forward pass ran (kslot[fine tile][entry
+// of the tile]): bits 5c .. 5c + 4 hold the kept slot (0..15) of corner c, 31 if absent or
+// not kept.
 constexpr uint32_t KSLOT_NONE = 31;
 
 // fwd_fine: one workgroup per fine tile, one entry per thread.  Fragments are counting-sorted
@@ -1137,9 +1135,9 @@ constexpr uint32_t KSLOT_NONE = 31;
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_fine(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
-    Entry* __restrict__ ent, const float* __restrict__ desc, float* __restrict__ pyr,
-    uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey, float* __restrict__ kgam,
-    const float* __restrict__ bg, float* __restrict__ alpha) {
+    const Entry* __restrict__ ent, uint32_t* __restrict__ kslot, const float* __restrict__ desc,
+    float* __restrict__ pyr, uint32_t* __restrict__ npix, uint64_t* __restrict__ kkey,
+    float* __restrict__ kgam, const float* __restrict__ bg, float* __restrict__ alpha) {
   constexpr int NF = 4 * FINE_E;     // fragment capacity
   __shared__ uint32_t hist[TP];      // fragments per texel, then the start of its run
   __shared__ uint32_t ws[4];
@@ -1168,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
 #pragma unroll
       for (int r4 = 0; r4 < D / 4; ++r4) dv[r4] = dp[r4];
     }
-    const uint32_t b = wk.x, e0 = wk.y;
+    const uint32_t b = wk.x;
     const BinInfo bi = decode_bin(P, b);
     hist[t] = 0;
     __syncthreads();
@@ -1225,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
         }
         packed |= m << (5 * c);
       }
-      ent[e0 + t].slot = (en.slot & 7u) | (packed << KSLOT_SHIFT);
+      kslot[size_t(blockIdx.x) * TP + t] = packed;
     }
     // blend front to back
     const uint32_t k = min(cnt, uint32_t(KEEP));
@@ -1677,9 +1675,9 @@ __global__ __launch_bounds__(256) void k_bwd_items(
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_fine(
     const Params P, const uint32_t* __restrict__ info, const uint4* __restrict__ fine_work,
-    const Entry* __restrict__ ent, const uint32_t* __restrict__ npix,
-    const float* __restrict__ desc, const float* __restrict__ gpyr, float* __restrict__ rows,
-    const Extras X) {
+    const Entry* __restrict__ ent, const uint32_t* __restrict__ kslot,
+    const uint32_t* __restrict__ npix, const float* __restrict__ desc,
+    const float* __restrict__ gpyr, float* __restrict__ rows, const Extras X) {
   constexpr int RW = 4 + D;
   constexpr int NF = 4 * FINE_E;  // at most one kept fragment per fragment
   __shared__ float s_G[TP][D + 1];
@@ -1696,7 +1694,11 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
   const BinInfo bi = decode_bin(P, b);
   const bool has = e0 + uint32_t(t) < e1;
   Entry en = {};
-  if (has) en = ent[e0 + t];
+  uint32_t packed = 0;  // kept slots of the entry's corners, as the forward pass recorded them
+  if (has) {
+    en = ent[e0 + t];
+    packed = kslot[size_t(blockIdx.x) * TP + t];
+  }
   const uint32_t k = min(npix[size_t(b) * TP + t], uint32_t(KEEP));
   // upstream gradient of the tile's texels inside the layer
   const int lth = 8 - P.ltw;
@@ -1723,7 +1725,6 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
   __syncthreads();
   Corner cs[4];
   uint32_t cm = has ? entry_corners(en, bi, P.ltw, cs) : 0u;
-  const uint32_t packed = en.slot >> KSLOT_SHIFT;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t m = (packed >> (5 * q)) & 31u;
@@ -2922,7 +2923,7 @@ struct Layout {
   uint64_t npyr;      // texels of all views and layers
   // saved buffer
   size_t s_info, s_bin_start, s_item_start, s_multi, s_fine, s_coarse, s_npix, s_kkey, s_kgam,
-      s_fkey, s_fgam, s_fcnt, s_tables_end, s_work, s_ent, s_epos;
+      s_fkey, s_fgam, s_fcnt, s_kslot, s_tables_end, s_work, s_ent, s_epos;
   size_t saved_bytes;
   // workspace
   size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, w_itot, w_iup,
@@ -3026,6 +3027,8 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.s_fkey = take(inc * NB * TP * KEEP * 8);
   lay.s_fgam = take(inc * NB * TP * KEEP * 4);
   lay.s_fcnt = take(inc * NB * TP * 4);
+  // kept slots of the entries of fine tiles (written by the forward, read by the backward)
+  lay.s_kslot = take((P.fine_e ? NB : 0) * TP * 4);
   lay.s_tables_end = o;
   // point-count dependent parts
   lay.s_work = take(size_t(lay.icap) * sizeof(uint4));
@@ -3180,6 +3183,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   float* kgam = reinterpret_cast<float*>(sv + lay.s_kgam);
   Entry* ent = reinterpret_cast<Entry*>(sv + lay.s_ent);
   uint32_t* epos = reinterpret_cast<uint32_t*>(sv + lay.s_epos);
+  uint32_t* kslot = reinterpret_cast<uint32_t*>(sv + lay.s_kslot);
 
   if (P.nblk > 0) {
     StageTimer tm(ST_COUNT, st);
@@ -3245,7 +3249,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
     {  // one workgroup per fine tile; workgroups beyond their count exit at once
       StageTimer tm(ST_FWD_FINE, sd->s);
       hipLaunchKernelGGL(k_fwd_fine<D>, dim3(P.NB), dim3(256), 0, sd->s, P, info, fine_work, ent,
-                         pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
+                         kslot, pts.desc, pyr, npix, kkey, kgam, X.bg, X.alpha);
     }
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipEventRecord(sd->join, sd->s);
@@ -3307,6 +3311,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   const float* kgam = reinterpret_cast<const float*>(sv + lay.s_kgam);
   const Entry* ent = reinterpret_cast<const Entry*>(sv + lay.s_ent);
   const uint32_t* epos = reinterpret_cast<const uint32_t*>(sv + lay.s_epos);
+  const uint32_t* kslot = reinterpret_cast<const uint32_t*>(sv + lay.s_kslot);
 
   if (P.coarser) {
     // finest layer first: every layer's items collect what the finer lists took from them
@@ -3369,7 +3374,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
     {
       StageTimer tm(ST_BWD_FINE, sd->s);
       hipLaunchKernelGGL(k_bwd_fine<D>, dim3(P.NB), dim3(256), 0, sd->s, P, info, fine_work, ent,
-                         npix, pts.desc, gpyr, rows, X);
+                         kslot, npix, pts.desc, gpyr, rows, X);
     }
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipEventRecord(sd->join, sd->s);
