@@ -83,7 +83,7 @@ def method_bytes(stage, w):
 
 def impl_bytes(stage, w):
     """The implementation's own byte model of one launch (reads + writes of its data
-    structures: 24-byte tile entries, 32-byte rows, per-block histograms, kept keys and
+    structures: 20-byte tile entries, 32-byte rows, per-block histograms, kept keys and
     gammas), for comparison with the method's bytes and the counters."""
     N, D, E, Ef, K, Kf, Nv = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"], w["Nv"]
     NB, NBf, Ic, Pc, Pf, nblk = w["NB"], w["NB_f"], w["I_c"], w["P_c"], w["P_f"], w["nblk"]
@@ -92,11 +92,11 @@ def impl_bytes(stage, w):
     table = {
         "count": 16 * N + 4 * nblk * NB,
         "colscan": 8 * nblk * NB + 4 * NB,
-        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 24 * E + 32 * Nv,
-        "fwd_items": 24 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
-        "fwd_fine": (28 + 4 * D) * Ef + 12 * Kf + 4 * 256 * NBf + 4 * D * Pf,
+        "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 20 * E + 32 * Nv,
+        "fwd_items": 20 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
+        "fwd_fine": (24 + 4 * D) * Ef + 12 * Kf + 4 * 256 * NBf + 4 * D * Pf,
         "bwd_pixels": 4 * 256 * NBc + (12 + 4 * D + 8) * Kc + 4 * D * Pc,
-        "bwd_items": (24 + row) * Ec + 16 * Kc + Ic * 256 * (4 + 4 * D),
+        "bwd_items": (20 + row) * Ec + 16 * Kc + Ic * 256 * (4 + 4 * D),
         "bwd_fine": (24 + 4 * D + row) * Ef + 4 * 256 * NBf + 4 * D * Pf,
         "bwd_points": 20 * N + 32 * Nv + row * E + 4 * (5 + D) * N,
     }
