@@ -9,8 +9,8 @@
 // ~27 G/s on this part, 1.3 G/s when contended, far below scattered stores):
 //   count      one workgroup per (point block, view): LDS histogram of tile entries
 //              (entry = one point's footprint part inside one 256-texel tile of one layer)
-//              -> one row of a per-block histogram matrix H[block][bin].
-//   colscan    per bin, exclusive prefix of H over blocks (in place) and bin totals.
+//              -> one row of a per-block histogram matrix H16[block][bin] (16-bit counts).
+//   colscan    per bin, exclusive prefix of H16 over blocks (32-bit, into H) and bin totals.
 //   binscan    exclusive scans of bin totals -> bin starts, and of work items -> item starts.
 //   scatter    same blocks again: LDS ranks, entry written at bin_start + H + rank.
 //   fwd_items  persistent: one workgroup per work item (a bin, or a chunk of a heavy bin);
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const flo
                                                        const float* __restrict__ Y,
                                                        const float* __restrict__ Z,
                                                        const float* __restrict__ SW,
-                                                       uint32_t* __restrict__ H) {
+                                                       uint16_t* __restrict__ H16) {
   extern __shared__ uint32_t hist[];
   const int v = blockIdx.x % P.V;
   const uint32_t blk = blockIdx.x / P.V;
@@ -378,9 +378,11 @@ __global__ __launch_bounds__(BIN_THREADS) void k_count(const Params P, const flo
     x = xn; y = yn; z = zn; sw = swn;
   }
   __syncthreads();
-  uint32_t* row = H + size_t(blk) * P.NB + c.bin_base;
+  // 16-bit counts: a block holds at most P.pb < 2^16 points, each with at most one entry
+  // per tile
+  uint16_t* row = H16 + size_t(blk) * P.NB + c.bin_base;
   for (uint32_t i = threadIdx.x; i < c.nbins; i += blockDim.x)
-    row[i] = (hist[i >> 1] >> ((i & 1u) * 16u)) & 0xffffu;
+    row[i] = uint16_t((hist[i >> 1] >> ((i & 1u) * 16u)) & 0xffffu);
 }
 
 // The tile scan over chunks of 64 tiles (one wavefront each): the chunk sums (written by the
@@ -453,12 +455,13 @@ __global__ __launch_bounds__(64) void k_chunksum(const uint32_t* __restrict__ to
   chunk_sums(tile_count(tot, b, NB, item_e, fine_e), item_e, csum + size_t(blockIdx.x) * CSUM);
 }
 
-// colscan: per bin, exclusive prefix of H over point blocks (in place) and the bin total;
+// colscan: per bin, exclusive prefix of H16 over point blocks (into H) and the bin total;
 // the wavefront that finishes the totals of its 64 bins (one chunk) also writes the chunk's
 // sums.  Workgroup = 64 bins x 16 block segments.
 constexpr int CS_SEG = 16;
 static_assert(CHUNK == 64, "a column-scan workgroup covers one chunk");
-__global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ H,
+__global__ __launch_bounds__(64 * CS_SEG) void k_colscan(const uint16_t* __restrict__ H16,
+                                                         uint32_t* __restrict__ H,
                                                          uint32_t* __restrict__ tot, uint32_t NB,
                                                          uint32_t nblk, uint32_t* __restrict__ csum,
                                                          uint32_t item_e, uint32_t fine_e) {
@@ -477,14 +480,14 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
   if (cached) {
     const uint32_t bb = min(b, NB - 1);
 #pragma unroll
-    for (uint32_t q = 0; q < RC; ++q) c[q] = H[size_t(min(k0 + q, k1 - 1)) * NB + bb];
+    for (uint32_t q = 0; q < RC; ++q) c[q] = H16[size_t(min(k0 + q, k1 - 1)) * NB + bb];
 #pragma unroll
     for (uint32_t q = 0; q < RC; ++q) sum += k0 + q < k1 && b < NB ? c[q] : 0u;
   } else if (b < NB) {
     for (uint32_t k = k0; k < k1; k += RB) {
       uint32_t v[RB];
 #pragma unroll
-      for (uint32_t q = 0; q < RB; ++q) v[q] = H[size_t(min(k + q, k1 - 1)) * NB + b];
+      for (uint32_t q = 0; q < RB; ++q) v[q] = H16[size_t(min(k + q, k1 - 1)) * NB + b];
 #pragma unroll
       for (uint32_t q = 0; q < RB; ++q) sum += k + q < k1 ? v[q] : 0u;
     }
@@ -509,7 +512,7 @@ __global__ __launch_bounds__(64 * CS_SEG) void k_colscan(uint32_t* __restrict__ 
     for (uint32_t k = k0; k < k1; k += RB) {
       uint32_t v[RB];
 #pragma unroll
-      for (uint32_t q = 0; q < RB; ++q) v[q] = H[size_t(min(k + q, k1 - 1)) * NB + b];
+      for (uint32_t q = 0; q < RB; ++q) v[q] = H16[size_t(min(k + q, k1 - 1)) * NB + b];
 #pragma unroll
       for (uint32_t q = 0; q < RB; ++q)
         if (k + q < k1) {
@@ -2926,7 +2929,7 @@ struct Layout {
       s_fkey, s_fgam, s_fcnt, s_kslot, s_tables_end, s_work, s_ent, s_epos;
   size_t saved_bytes;
   // workspace
-  size_t w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, w_itot, w_iup,
+  size_t w_H16, w_H, w_tot, w_csum, w_coff, w_pcnt, w_pkey, w_pgam, w_bst, w_rows, w_cam, w_itot, w_iup,
       ws_bytes;
   size_t ws_fwd_bytes;  // the part of the workspace a forward call uses
 };
@@ -3038,7 +3041,8 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   o = 0;
   const size_t scratch = o;
   // forward scratch
-  lay.w_H = take(size_t(P.nblk) * NB * 4);
+  lay.w_H16 = take(size_t(P.nblk) * NB * 2);  // per-block counts per tile
+  lay.w_H = take(size_t(P.nblk) * NB * 4);    // their exclusive prefixes over blocks
   lay.w_tot = take(NB * 4);
   lay.w_csum = take(((NB + CHUNK - 1) / CHUNK) * CSUM * 4);
   lay.w_coff = take(((NB + CHUNK - 1) / CHUNK) * 4 * 4);
@@ -3163,6 +3167,7 @@ template <int D>
 trips_status launch_forward(const Layout& lay, const trips_points& pts, float* pyr, char* sv,
                             char* ws, const Extras& X, hipStream_t st) {
   const Params& P = lay.P;
+  uint16_t* H16 = reinterpret_cast<uint16_t*>(ws + lay.w_H16);
   uint32_t* H = reinterpret_cast<uint32_t*>(ws + lay.w_H);
   uint32_t* tot = reinterpret_cast<uint32_t*>(ws + lay.w_tot);
   const uint32_t nch = (P.NB + CHUNK - 1) / CHUNK;
@@ -3188,13 +3193,13 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
   if (P.nblk > 0) {
     StageTimer tm(ST_COUNT, st);
     hipLaunchKernelGGL(k_count, dim3(P.nblk * P.V), dim3(BIN_THREADS), count_lds(lay.nbv_max), st,
-                       P, pts.x, pts.y, pts.z, pts.size_w, H);
+                       P, pts.x, pts.y, pts.z, pts.size_w, H16);
   }
   TRIPS_HIP(hipGetLastError());
   {
     StageTimer tm(ST_COLSCAN, st);
     if (P.nblk > 0) {  // also writes the chunk sums
-      hipLaunchKernelGGL(k_colscan, dim3((P.NB + 63) / 64), dim3(64 * CS_SEG), 0, st, H, tot,
+      hipLaunchKernelGGL(k_colscan, dim3((P.NB + 63) / 64), dim3(64 * CS_SEG), 0, st, H16, H, tot,
                          P.NB, P.nblk, csum, P.item_e, P.fine_e);
     } else {
       hipLaunchKernelGGL(k_fill_u32, dim3((P.NB + 255) / 256), dim3(256), 0, st, tot, P.NB, 0u);
