@@ -83,15 +83,16 @@ def method_bytes(stage, w):
 
 def impl_bytes(stage, w):
     """The implementation's own byte model of one launch (reads + writes of its data
-    structures: 20-byte tile entries, 32-byte rows, per-block histograms, kept keys and
+    structures: 20-byte tile entries, 32-byte rows, 16-bit per-block histograms and their
+    32-bit prefixes, kept keys and
     gammas), for comparison with the method's bytes and the counters."""
     N, D, E, Ef, K, Kf, Nv = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"], w["Nv"]
     NB, NBf, Ic, Pc, Pf, nblk = w["NB"], w["NB_f"], w["I_c"], w["P_c"], w["P_f"], w["nblk"]
     Ec, Kc, NBc = E - Ef, K - Kf, NB - NBf
     row = 4 * (4 + D)
     table = {
-        "count": 16 * N + 4 * nblk * NB,
-        "colscan": 8 * nblk * NB + 4 * NB,
+        "count": 16 * N + 2 * nblk * NB,
+        "colscan": 6 * nblk * NB + 4 * NB,
         "scatter": 20 * N + 4 * nblk * NB + 4 * NB + 20 * E + 32 * Nv,
         "fwd_items": 20 * Ec + (4 * D + 12) * Kc + 4 * 256 * NBc + 4 * D * Pc,
         "fwd_fine": (24 + 4 * D) * Ef + 12 * Kf + 4 * 256 * NBf + 4 * D * Pf,
