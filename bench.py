@@ -84,8 +84,8 @@ def method_bytes(stage, w):
 def impl_bytes(stage, w):
     """The implementation's own byte model of one launch (reads + writes of its data
     structures: 20-byte tile entries, 32-byte rows, 16-bit per-block histograms and their
-    32-bit prefixes, kept keys and
-    gammas), for comparison with the method's bytes and the counters."""
+    32-bit prefixes, kept keys and gammas), for comparison with the method's bytes and the
+    counters."""
     N, D, E, Ef, K, Kf, Nv = w["N"], w["D"], w["E"], w["E_f"], w["K"], w["K_f"], w["Nv"]
     NB, NBf, Ic, Pc, Pf, nblk = w["NB"], w["NB_f"], w["I_c"], w["P_c"], w["P_f"], w["nblk"]
     Ec, Kc, NBc = E - Ef, K - Kf, NB - NBf
