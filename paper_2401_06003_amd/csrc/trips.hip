@@ -52,6 +52,11 @@ constexpr uint64_t KEY_NONE = ~0ull;
 constexpr uint32_t FINE_E = 256;
 // The backward needs no merge, so its workgroups take smaller parts of the work items.
 constexpr uint32_t BWD_SPLIT = 2;
+// Workgroups are dealt to the chip's 8 dies (XCDs, each with its own L2) in turn by index;
+// kernels that share data between workgroups place them 8 indices apart.  The work-item
+// capacity is a multiple of it.
+constexpr uint32_t XCDS = 8;
+constexpr uint32_t PT_GROUP = 16;  // point chunks of the point pass kept on one die
 // Work items are ordered by size class, largest first: class q holds items of more than
 // (NBUCKET - 1 - q) / NBUCKET of item_e entries.  info[INFO_BUCKET + q] is the first work
 // slot of class q, info[INFO_BUCKET + NBUCKET + q] its fill counter.
@@ -1543,8 +1548,12 @@ __global__ __launch_bounds__(256) void k_bwd_items(
   __shared__ float s_G[TP][D + 1];
   const int t = threadIdx.x;
   const uint32_t total = info[1];
-  // every work item is shared by `split` workgroups, each taking an equal part of its entries
-  const uint32_t wi = blockIdx.x / split, part = blockIdx.x % split;
+  // every work item is shared by `split` workgroups, each taking an equal part of its entries;
+  // the parts of an item are XCDS indices apart (the same die, so the tile's lists and blend
+  // adjoints are fetched into one L2): workgroup g XCDS split + XCDS p + q takes part p of
+  // item g XCDS + q
+  const uint32_t grp = blockIdx.x / (XCDS * split), rem = blockIdx.x % (XCDS * split);
+  const uint32_t wi = grp * XCDS + rem % XCDS, part = rem / XCDS;
   const uint4 wk = work[wi];  // in bounds (grid = split x capacity); used only if valid
   if (wi >= total) return;
   const uint32_t b = wk.x;
@@ -2728,7 +2737,14 @@ __global__ __launch_bounds__(256) void k_bwd_points(
     float* __restrict__ gD, const uint32_t* __restrict__ epos, float* __restrict__ campart) {
   constexpr int RW = 4 + D;
   __shared__ float s_cam[CAM ? 4 : 1][16];
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // chunks of 256 points go to the dies in runs of PT_GROUP consecutive chunks (about one
+  // scatter block, whose entries' rows share lines): workgroup g XCDS PT_GROUP + XCDS j + q
+  // takes chunk (g XCDS + q) PT_GROUP + j; the grid is padded to a multiple of XCDS PT_GROUP
+  const uint32_t span = XCDS * PT_GROUP;
+  const uint32_t chunk = (blockIdx.x / span * XCDS + blockIdx.x % XCDS) * PT_GROUP +
+                         blockIdx.x % span / XCDS;
+  if (int64_t(chunk) * blockDim.x >= P.n) return;  // (uniform: a padding workgroup)
+  const int64_t p = int64_t(chunk) * blockDim.x + threadIdx.x;
   const bool live = p < P.n;
   if (!CAM && !live) return;
   float x = 0.f, y = 0.f, z = 0.f, sw = 0.f, alpha = 0.f;
@@ -2831,7 +2847,7 @@ __global__ __launch_bounds__(256) void k_bwd_points(
       }
       __syncthreads();
       if (threadIdx.x < 16)
-        campart[(size_t(blockIdx.x) * P.V + v) * 16 + threadIdx.x] =
+        campart[(size_t(chunk) * P.V + v) * 16 + threadIdx.x] =
             ((s_cam[0][threadIdx.x] + s_cam[1][threadIdx.x]) + s_cam[2][threadIdx.x]) + s_cam[3][threadIdx.x];
       __syncthreads();
     }
@@ -3011,6 +3027,7 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   lay.ecap = 8ull * uint64_t(n) * uint64_t(views);  // <= 2 layers x 4 tiles per point and view
   if (lay.ecap >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
   lay.icap = bins + (lay.ecap + item_e - 1) / item_e;
+  lay.icap = (lay.icap + XCDS - 1) / XCDS * XCDS;
   if (lay.icap * BWD_SPLIT >= (1ull << 32) - 1) return TRIPS_ERR_CAPACITY;
   const size_t NB = bins;
   size_t o = 0;
@@ -3400,13 +3417,14 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
   if (P.n > 0) {
     StageTimer tm(ST_BWD_POINTS, st);
     const uint32_t nblk = uint32_t((P.n + 255) / 256);
+    const uint32_t grid = (nblk + XCDS * PT_GROUP - 1) / (XCDS * PT_GROUP) * (XCDS * PT_GROUP);
     float* campart = reinterpret_cast<float*>(ws + lay.w_cam);
     if (X.gcam)
-      hipLaunchKernelGGL((k_bwd_points<D, true>), dim3(nblk), dim3(256), 0, st, P, pts.x, pts.y,
+      hipLaunchKernelGGL((k_bwd_points<D, true>), dim3(grid), dim3(256), 0, st, P, pts.x, pts.y,
                          pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, epos,
                          campart);
     else
-      hipLaunchKernelGGL((k_bwd_points<D, false>), dim3(nblk), dim3(256), 0, st, P, pts.x, pts.y,
+      hipLaunchKernelGGL((k_bwd_points<D, false>), dim3(grid), dim3(256), 0, st, P, pts.x, pts.y,
                          pts.z, pts.size_w, pts.opacity, rows, gx, gy, gz, gsw, ga, gd, epos,
                          campart);
   }
