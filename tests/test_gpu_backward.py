@@ -52,6 +52,15 @@ def test_unit_cube_4096(gpu):
     _check(scenes.unit_cube(1), gpu, 1)
 
 
+def test_spatially_ordered_points(gpu):
+    """A Morton-ordered cluster scene (consecutive points crowd the same texels) with work
+    items small enough that heavy tiles are cut into several."""
+    import paper_2401_06003_amd as tp
+    sc = scenes.morton_sorted(scenes.cluster_scene(6, n=30_000, W=240, H=136, nlayers=5,
+                                                   s_hi=48.0))
+    _check(sc, gpu, 4, tp.make_tuning(16, 0, 512))
+
+
 def test_descriptor_width_8(gpu):
     _check(scenes.unit_cube(5, n=2000, W=120, H=90, nlayers=5, D=8), gpu, 2)
 
