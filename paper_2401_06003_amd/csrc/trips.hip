@@ -57,6 +57,20 @@ constexpr uint32_t BWD_SPLIT = 2;
 // capacity is a multiple of it.
 constexpr uint32_t XCDS = 8;
 constexpr uint32_t PT_GROUP = 16;  // point chunks of the point pass kept on one die
+// Tile (tx, ty) of a layer with tiles_x x tiles_y tiles for workgroup b of a per-tile pass
+// whose tiles read the lists of the next coarser layer: the 2x2 tiles under one coarser tile
+// share them, so they go to one die.  Quads are numbered row-major; quad q's four tiles are
+// workgroups (q / XCDS) 4 XCDS + XCDS m + q % XCDS, m = 2 (row in quad) + column.  False
+// for a workgroup past the layer's tiles.
+__device__ __forceinline__ bool quad_tile(uint32_t b, int tiles_x, int tiles_y, int& tx, int& ty) {
+  constexpr uint32_t span = 4 * XCDS;
+  const uint32_t q = b / span * XCDS + b % XCDS, m = b % span / XCDS;
+  const uint32_t qx_n = uint32_t(tiles_x + 1) / 2;
+  const uint32_t qy = q / qx_n, qx = q % qx_n;
+  tx = int(2 * qx + (m & 1u));
+  ty = int(2 * qy + (m >> 1));
+  return tx < tiles_x && ty < tiles_y;
+}
 // Work items are ordered by size class, largest first: class q holds items of more than
 // (NBUCKET - 1 - q) / NBUCKET of item_e entries.  info[INFO_BUCKET + q] is the first work
 // slot of class q, info[INFO_BUCKET + NBUCKET + q] its fill counter.
@@ -100,7 +114,7 @@ static_assert(sizeof(Entry) == 20, "entry layout");
 // texels, which corners exist) and must match any other correct single-precision
 // evaluation of the same sequence.
 
-__device__ __forceinline__ int layer_dim(int W, int L) { return (W + (1 << L) - 1) >> L; }
+__host__ __device__ __forceinline__ int layer_dim(int W, int L) { return (W + (1 << L) - 1) >> L; }
 __device__ __forceinline__ float pow2i(int e) { return __int_as_float((127 + e) << 23); }
 
 struct Geo {
@@ -1849,14 +1863,13 @@ __global__ __launch_bounds__(256) void k_incl_fwd(
   __shared__ uint32_t s_pn[PT];
   const int v = blockIdx.y;
   const ViewP& c = P.view[v];
-  const uint32_t local = blockIdx.x;
-  if (local >= c.lbin[L + 1] - c.lbin[L]) return;  // uniform per workgroup
-  const uint32_t b = c.lbin[L] + local;
   const int t = threadIdx.x;
   const int lth = 8 - P.ltw;
   const int WL = layer_dim(c.W, L), HL = layer_dim(c.H, L);
-  const int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw;
-  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  const int tiles_x = (WL + (1 << P.ltw) - 1) >> P.ltw, tiles_y = (HL + (1 << lth) - 1) >> lth;
+  int tx, ty;  // the four tiles under one covering tile on one die
+  if (!quad_tile(blockIdx.x, tiles_x, tiles_y, tx, ty)) return;  // uniform per workgroup
+  const uint32_t b = c.lbin[L] + uint32_t(ty * tiles_x + tx);
   const int i = (tx << P.ltw) + (t & ((1 << P.ltw) - 1));
   const int j = (ty << lth) + (t >> P.ltw);
   const bool in = i < WL && j < HL;
@@ -2569,15 +2582,14 @@ __global__ __launch_bounds__(256) void k_incl_bwd012(
   __shared__ float s_up[PT][KEEP][S];  // totals of the block's layer-2 texels
   const int v = blockIdx.y;
   const ViewP& c = P.view[v];
-  const uint32_t local = blockIdx.x;
-  if (local >= c.lbin[2] - c.lbin[1]) return;  // uniform per workgroup
-  const uint32_t b = c.lbin[1] + local;
   const int t = threadIdx.x;
   const int ltw = P.ltw, lth = 8 - P.ltw;
   const int W1 = layer_dim(c.W, 1), H1 = layer_dim(c.H, 1);
   const int W0 = layer_dim(c.W, 0), H0 = layer_dim(c.H, 0);
-  const int tiles_x = (W1 + (1 << ltw) - 1) >> ltw;
-  const int ty = int(local) / tiles_x, tx = int(local) - ty * tiles_x;
+  const int tiles_x = (W1 + (1 << ltw) - 1) >> ltw, tiles_y = (H1 + (1 << lth) - 1) >> lth;
+  int tx, ty;  // the four tiles under one layer-2 tile on one die
+  if (!quad_tile(blockIdx.x, tiles_x, tiles_y, tx, ty)) return;  // uniform per workgroup
+  const uint32_t b = c.lbin[1] + uint32_t(ty * tiles_x + tx);
   const int i = (tx << ltw) + (t & ((1 << ltw) - 1));
   const int j = (ty << lth) + (t >> ltw);
   const bool in = i < W1 && j < H1;
@@ -3179,6 +3191,16 @@ uint32_t layer_tiles_max(const Params& P, int L) {
   for (int v = 0; v < P.V; ++v) m = std::max(m, P.view[v].lbin[L + 1] - P.view[v].lbin[L]);
   return m;
 }
+// grid of a pass laid out by quad_tile over layer L: every view's quads, 4 XCDS per XCDS quads
+uint32_t layer_quad_grid(const Params& P, int L) {
+  uint32_t m = 0;
+  for (int v = 0; v < P.V; ++v) {
+    const uint32_t WL = uint32_t(layer_dim(P.view[v].W, L)), HL = uint32_t(layer_dim(P.view[v].H, L));
+    const uint32_t tx = (WL + (1u << P.ltw) - 1) >> P.ltw, ty = (HL + (1u << (8 - P.ltw)) - 1) >> (8 - P.ltw);
+    m = std::max(m, ((tx + 1) / 2) * ((ty + 1) / 2));
+  }
+  return (m + XCDS - 1) / XCDS * (4 * XCDS);
+}
 
 template <int D>
 trips_status launch_forward(const Layout& lay, const trips_points& pts, float* pyr, char* sv,
@@ -3308,7 +3330,7 @@ trips_status launch_forward(const Layout& lay, const trips_points& pts, float* p
       L = Lb - 1;
     }
     for (; L >= 0; --L) {
-      hipLaunchKernelGGL(k_incl_fwd<D>, dim3(layer_tiles_max(P, L), uint32_t(P.V)), dim3(256), 0,
+      hipLaunchKernelGGL(k_incl_fwd<D>, dim3(layer_quad_grid(P, L), uint32_t(P.V)), dim3(256), 0,
                          st, P, L, npix, kkey, kgam, fkey, fgam, fcnt, pts.desc, pyr, X.bg,
                          X.alpha);
       TRIPS_HIP(hipGetLastError());
@@ -3349,7 +3371,7 @@ trips_status launch_backward(const Layout& lay, const trips_points& pts, const f
       // memory)
       const bool fuse = P.nl > 1;
       if (fuse) {
-        hipLaunchKernelGGL(k_incl_bwd012<D>, dim3(layer_tiles_max(P, 1), uint32_t(P.V)), dim3(256),
+        hipLaunchKernelGGL(k_incl_bwd012<D>, dim3(layer_quad_grid(P, 1), uint32_t(P.V)), dim3(256),
                            0, st, P, fkey, fgam, kkey, kgam, fcnt, pts.desc, gpyr, itot, iup, X);
         TRIPS_HIP(hipGetLastError());
       }
