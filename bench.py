@@ -749,6 +749,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom),
+                     # the counters' HBM bytes over the same time: what the kernel moves, not
+                     # what the method needs (a re-read counts twice here)
+                     "traffic_frac": (measured_traffic(dom) / (stage_ms[dom] / 1e3) / 1e9
+                                      / HBM_PEAK_GBS if measured_traffic(dom) else None),
                      "bytes_per_launch": dom_bytes, "ms_per_launch": stage_ms[dom],
                      "impl_bytes_per_launch": impl_bytes(dom, w),
                      "step_frac": sbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
@@ -758,6 +762,7 @@ def main():
         "step_algorithmic_bytes": sbytes,
         "step_measured_hbm_bytes": step_meas,
         "step_measured_over_algorithmic": (step_meas / sbytes if step_meas else None),
+        "step_counter_hbm_frac": (step_meas / (ms / 1e3) / 1e9 / HBM_PEAK_GBS if step_meas else None),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "stage_method_gbps": {k: round(method_bytes(k, w) / (v / 1e3) / 1e9, 1)
                               for k, v in stage_ms.items() if method_bytes(k, w)},
