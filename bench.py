@@ -249,8 +249,9 @@ def cpu_baseline(sc, G, runs=3):
 
 def run_small_latency(torch, tp, scenes, steps, dev):
     """4096 points in the unit cube, 256x256, 5 layers: forward alone and forward + backward
-    latency of direct launches (microseconds), and the oracle's forward on one and on every
-    host thread (median of 3)."""
+    latency (microseconds) of direct launches and of a captured graph's replays, the same
+    with the autotuner's launch shape, and the oracle's forward on one and on every host
+    thread (median of 3)."""
     import numpy as np
     from oracle import oracle, parallel
     sc = scenes.unit_cube(1)
@@ -268,11 +269,34 @@ def run_small_latency(torch, tp, scenes, steps, dev):
     fwd_ms = timed(torch, lambda: r.forward(*args, out=pyr), steps)
     fb_ms = timed(torch, lambda: (r.forward(*args, out=pyr), r.backward(*args, G, outs=grads)),
                   steps)
+    # the same calls captured once in a HIP graph and replayed (no per-call host work)
+    plan = tp.Plan(r, *args, pyr, G, grads)
+    for _ in range(3):
+        plan.launch(forward=True, backward=True)
+    fwd_graph_ms = timed(torch, lambda: plan.launch(forward=True, backward=False), steps)
+    fb_graph_ms = timed(torch, lambda: plan.launch(forward=True, backward=True), steps)
+    del plan
+    # the autotuner's launch shape for this workload: smaller binning blocks and work items
+    # spread a few heavy tiles over more workgroups
+    cand = [(tw, pb, ie) for tw in (8, 16) for pb in (512, 1024, 4096) for ie in (256, 512, 1024, 8192)]
+    best, _ = tp.autotune([cam], nl, D, *args, candidates=cand, reps=5, device=dev)
+    rt = tp.Renderer([cam], nl, D, n, tuning=best, device=dev)
+    for _ in range(5):
+        rt.forward(*args, out=pyr)
+        rt.backward(*args, G, outs=grads)
+    tfwd_ms = timed(torch, lambda: rt.forward(*args, out=pyr), steps)
+    tfb_ms = timed(torch, lambda: (rt.forward(*args, out=pyr), rt.backward(*args, G, outs=grads)),
+                   steps)
+    del rt
     one, _ = median_time(lambda: oracle.forward(sc["points"], cam, nl), 3)
     workers = parallel.default_workers()
     par, _ = median_time(lambda: parallel.forward(sc["points"], cam, nl, workers=workers), 3)
     return {"workload": "unitcube4096_256x256_5layers_d4", "points": n,
             "forward_us": fwd_ms * 1e3, "fwd_bwd_us": fb_ms * 1e3,
+            "forward_us_graph": fwd_graph_ms * 1e3, "fwd_bwd_us_graph": fb_graph_ms * 1e3,
+            "tuned": {"tile_w": best.tile_w, "points_per_block": best.points_per_block,
+                      "item_entries": best.item_entries, "forward_us": tfwd_ms * 1e3,
+                      "fwd_bwd_us": tfb_ms * 1e3},
             "oracle_forward_us_1core": one * 1e6, "oracle_forward_us_all_cores": par * 1e6,
             "oracle_cores": workers}
 
