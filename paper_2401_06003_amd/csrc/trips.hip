@@ -1174,6 +1174,19 @@ __global__ __launch_bounds__(256) void k_fwd_fine(
   const int t = threadIdx.x;
   const uint4 wk = fine_work[blockIdx.x];  // in bounds (grid = bin count); used only if valid
   if (blockIdx.x >= info[4]) return;
+  if (wk.y == wk.z) {  // an empty tile (uniform): only the background shows
+    const BinInfo bi = decode_bin(P, wk.x);
+    const int lth = 8 - P.ltw;
+    const int i = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+    const int j = (bi.ty << lth) + (t >> P.ltw);
+    float C[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) C[d] = 0.0f;
+    if (i < bi.WL && j < bi.HL)
+      write_texel<D>(C, 1.0f, size_t(P.view[bi.v].lout[bi.L]) + size_t(j) * bi.WL + i, pyr, bg, alpha);
+    npix[size_t(wk.x) * TP + t] = 0;
+    return;
+  }
   const bool has = wk.y + uint32_t(t) < wk.z;
   Entry en = {};
   if (has) en = ent[wk.y + t];
@@ -1718,6 +1731,21 @@ __global__ __launch_bounds__(256) void k_bwd_fine(
   if (blockIdx.x >= info[4]) return;
   const uint32_t b = wk.x, e0 = wk.y, e1 = wk.z;
   const BinInfo bi = decode_bin(P, b);
+  if (e0 == e1) {  // an empty tile (uniform): only the background gradient, T G with T = 1
+    if (X.gbg) {
+      const int lth = 8 - P.ltw;
+      const int ti = (bi.tx << P.ltw) + (t & ((1 << P.ltw) - 1));
+      const int tj = (bi.ty << lth) + (t >> P.ltw);
+      if (ti < bi.WL && tj < bi.HL) {
+        const size_t tex = size_t(P.view[bi.v].lout[bi.L]) + size_t(tj) * bi.WL + ti;
+        float G[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) G[d] = gpyr[tex * D + d];
+        write_scaled<D>(X.gbg + tex * D, 1.0f, G);
+      }
+    }
+    return;
+  }
   const bool has = e0 + uint32_t(t) < e1;
   Entry en = {};
   uint32_t packed = 0;  // kept slots of the entry's corners, as the forward pass recorded them
