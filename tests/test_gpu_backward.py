@@ -52,6 +52,13 @@ def test_unit_cube_4096(gpu):
     _check(scenes.unit_cube(1), gpu, 1)
 
 
+def test_unit_cube_4096_small_launch_shape(gpu):
+    """At the autotuner's launch shape for this workload (8x32 tiles, 512-point blocks,
+    256-entry items)."""
+    import paper_2401_06003_amd as tp
+    _check(scenes.unit_cube(1), gpu, 1, tp.make_tuning(8, 512, 256))
+
+
 def test_spatially_ordered_points(gpu):
     """A Morton-ordered cluster scene (consecutive points crowd the same texels) with work
     items small enough that heavy tiles are cut into several."""

@@ -46,6 +46,16 @@ def test_unit_cube_4096(gpu):
     assert res[0][1].sum() > 20000
 
 
+def test_unit_cube_4096_small_launch_shape(gpu):
+    """The same workload at the launch shape the autotuner picks for it: 8x32 tiles, 512-point
+    binning blocks (eight blocks) and 256-entry work items, so the heavy coarse tiles are cut
+    into many items whose partial lists are merged."""
+    sc = scenes.unit_cube(1)
+    res, r, _ = check_forward(sc, gpu, _tune(8, 512, 256))
+    st = r.stats()
+    assert st["items"] > st["bins"]
+
+
 def test_descriptor_width_8(gpu):
     sc = scenes.unit_cube(5, n=2000, W=120, H=90, nlayers=5, D=8)
     check_forward(sc, gpu)
