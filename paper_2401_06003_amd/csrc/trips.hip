@@ -1086,12 +1086,14 @@ __global__ __launch_bounds__(256) void k_fwd_items(
         const uint32_t r1 = p + 1 < TP ? th[p + 1] >> TALLY_BITS : tot;
         const uint64_t ko = skey[o];
         uint32_t rk = 0;
-        for (uint32_t r = r0; r < r1; r += 4) {
-          uint64_t kq[4];
+        // eight keys per step, every read inside the run (the compares past its end are
+        // masked): long runs of crowded texels are latency-bound LDS chains
+        for (uint32_t r = r0; r < r1; r += 8) {
+          uint64_t kq[8];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) kq[q] = r + q < r1 ? skey[r + q] : KEY_NONE;
+          for (int q = 0; q < 8; ++q) kq[q] = skey[min(r + q, r1 - 1)];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) rk += kq[q] < ko ? 1u : 0u;
+          for (int q = 0; q < 8; ++q) rk += (r + q < r1 && kq[q] < ko) ? 1u : 0u;
         }
         if (rk < KEEP) sord[r0 + rk] = uint16_t(o - r0);
       }
