@@ -381,7 +381,8 @@ def run_coarser(torch, tp, sc, pargs, G, steps, warmup, dev, ms_plain):
 
 def run_points_8m(torch, tp, scenes, steps, warmup, dev):
     """The headline recipe with 8M points (1920x1080, 8 layers, D = 4, forward + backward),
-    launched directly, with the whole step's effective fraction of HBM peak."""
+    launched directly, with the whole step's effective fraction of HBM peak; then the same with
+    the autotuner's launch shape for this size."""
     sc = scenes.cluster_scene(2, n=8_000_000)
     cam, nl, D = sc["cams"][0], sc["nlayers"], sc["D"]
     n = len(sc["points"]["x"])
@@ -402,13 +403,31 @@ def run_points_8m(torch, tp, scenes, steps, warmup, dev):
     w = workload_counts(tp, r, [cam], nl, n, D)
     stage_ms, _ = stage_times(torch, tp, step, steps)
     sb = step_bytes(n, w["Nv"], D, w["F"], w["K"], w["P"])
+    del r
+    # the autotuner's launch shape for this size (four times the headline's entries per tile)
+    cand = [(16, pb, ie) for pb in (4096, 8192) for ie in (8192, 16384, 32768)]
+    best, _ = tp.autotune([cam], nl, D, *args, candidates=cand, reps=3, device=dev)
+    rt = tp.Renderer([cam], nl, D, n, tuning=best, device=dev)
+
+    def step_tuned():
+        rt.forward(*args, out=pyr)
+        rt.backward(*args, G, outs=grads)
+
+    for _ in range(warmup):
+        step_tuned()
+    ms_t = timed(torch, step_tuned, steps)
+    del rt
     return {"workload": "clusters8m_1920x1080_8layers_d4_fwd_bwd", "points": n,
             "ms_per_step": ms, "points_per_s": n / (ms / 1e3),
             "step_algorithmic_bytes": sb,
             "step_effective_hbm_frac": sb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "fragments": w["F"], "kept_fragments": w["K"], "visible_points": w["Nv"],
             "tile_entries": w["E"],
-            "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()}}
+            "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+            "tuned": {"tile_w": best.tile_w, "points_per_block": best.points_per_block,
+                      "item_entries": best.item_entries, "ms_per_step": ms_t,
+                      "points_per_s": n / (ms_t / 1e3),
+                      "step_effective_hbm_frac": sb / (ms_t / 1e3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def run_ordered(torch, tp, scenes, sc, G, steps, warmup, dev):

@@ -94,7 +94,8 @@ typedef struct {
    256 texels: 8x32, 16x16, 32x8, 64x4).  points_per_block is the number of points one
    binning workgroup histograms (256..65535, default 4096).  item_entries is the number of
    tile entries one sort/blend workgroup consumes before handing over to a merge
-   (256..65536, default 8192). */
+   (256..65536; default 8192 for up to one point per pixel of the largest view, doubled for
+   each doubling of that density, up to 32768). */
 typedef struct {
   int32_t tile_w;
   int32_t points_per_block;

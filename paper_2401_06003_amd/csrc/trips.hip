@@ -3011,6 +3011,15 @@ trips_status make_layout(const trips_config* cfg, const trips_camera* cams, int3
   if (cfg->max_list != KEEP) return TRIPS_ERR_UNSUPPORTED;
   if (cfg->desc_dim != 4 && cfg->desc_dim != 8) return TRIPS_ERR_UNSUPPORTED;
   int tile_w = 16, pb = 4096, item_e = 8192;
+  {
+    // default work-item size: 8192 entries up to one point per pixel of the largest view,
+    // doubled for each doubling of that density, up to 32768 (denser clouds put more entries
+    // in every tile, and smaller items then spend more on merges than they save)
+    int64_t px = 0;
+    for (int v = 0; v < views; ++v)
+      px = std::max<int64_t>(px, int64_t(cams[v].width) * cams[v].height);
+    while (item_e < 32768 && px > 0 && n > int64_t(item_e / 8192) * px) item_e *= 2;
+  }
   if (tun) {
     if (tun->tile_w) tile_w = tun->tile_w;
     if (tun->points_per_block) pb = tun->points_per_block;
