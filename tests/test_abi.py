@@ -66,6 +66,33 @@ def test_invalid_arguments(cfg, views, n, tune, code):
     assert st == code
 
 
+PX = 1024 * 768
+
+
+@pytest.mark.parametrize("n, item", [(1, 8192), (PX, 8192), (PX + 1, 16384), (2 * PX, 16384),
+                                     (2 * PX + 1, 32768), (4 * PX, 32768), (10 * PX, 32768)])
+def test_default_item_size_follows_density(n, item):
+    """The default work-item size is 8192 entries up to one point per pixel of the largest
+    view (1024x768 here; the smaller second view does not count), doubled for each doubling
+    of the density, up to 32768: the buffers equal those of that explicit size."""
+    tp, L = _lib()
+    cams = (tp.Camera * 2)(tp.make_camera(_cam(1024, 768)), tp.make_camera(_cam(512, 384)))
+    cfg = tp.make_config(5, 4)
+    sizes = []
+    for t in (None, tp.make_tuning(0, 0, item)):
+        ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+        assert L.trips_buffer_sizes(ctypes.byref(cfg), cams, 2, n, ctypes.byref(t) if t else None,
+                                    ctypes.byref(ws), ctypes.byref(sv)) == 0
+        sizes.append((ws.value, sv.value))
+    assert sizes[0] == sizes[1]
+    if item < 32768 and n >= PX:  # and differ from the next size up (the check has teeth)
+        ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+        up = tp.make_tuning(0, 0, 2 * item)
+        assert L.trips_buffer_sizes(ctypes.byref(cfg), cams, 2, n, ctypes.byref(up),
+                                    ctypes.byref(ws), ctypes.byref(sv)) == 0
+        assert (ws.value, sv.value) != sizes[0]
+
+
 def test_inclusion_flag_sizes_and_range():
     tp, L = _lib()
     cams = (tp.Camera * 1)(tp.make_camera(_cam(64, 48)))
