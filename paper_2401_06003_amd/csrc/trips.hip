@@ -1567,7 +1567,7 @@ __global__ __launch_bounds__(256) void k_bwd_items(
     uint32_t split, const uint32_t* __restrict__ fcnt, const float* __restrict__ itot) {
   constexpr int RW = 4 + D;
   constexpr int S = D + 1;
-  constexpr int EB = 2;  // entries per thread in flight
+  constexpr int EB = 3;  // entries per thread in flight
   __shared__ uint32_t s_k[TP];
   __shared__ uint64_t s_last[TP];
   // kept point ids, four per 16 bytes, quarter-list major: the reads of one quarter by lanes
