@@ -924,7 +924,7 @@ __device__ __forceinline__ void finalize_texel(const Params& P, const BinInfo& b
 constexpr int EPT = 2;                // entries per thread per LDS round
 constexpr int SUB_E = EPT * TP;       // entries per LDS round
 constexpr int SUB_F = 4 * SUB_E;      // fragments per LDS round (at most 4 per entry)
-constexpr uint32_t ENT_BLK = 16;      // consecutive entries taken together by fwd_items
+constexpr uint32_t ENT_BLK = 4;       // consecutive entries taken together by fwd_items
 constexpr uint32_t RND_BLK = SUB_E / ENT_BLK;  // blocks per round
 
 // Compare-exchange of (key, gamma) pairs: afterwards a holds the smaller key.
